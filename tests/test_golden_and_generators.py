@@ -1,0 +1,99 @@
+"""Hand-worked fixtures and the paper's printed table values (tests/golden/),
+plus determinism and structure checks of the seeded input generators."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("case", load("hand_worked.json")["graphs"], ids=lambda c: c["name"])
+def test_hand_worked_betweenness(case):
+    e = np.array(case["edges"])
+    g = gg.from_pairs(case["n"], e[:, 0], e[:, 1])
+    raw, _ = oracle.bc(g)
+    assert np.allclose(raw / 2, case["undirected_bc"], rtol=0, atol=1e-12)
+    assert np.array_equal(raw[np.array(case["undirected_bc"]) == 0], np.zeros(int(np.sum(np.array(case["undirected_bc"]) == 0))))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("ef,key", [(16, "table4_rmat20_ef16_one_degree_percent"),
+                                    (4, "table4_rmat20_ef4_one_degree_percent")])
+def test_rmat_degree_one_share_matches_table4(ef, key):
+    """Loose generator check: the share of degree-1 vertices of the paper's
+    R-MAT recipe at SCALE 20 is printed in Table 4."""
+    ref = load("paper_tables.json")[key]["value"]
+    g = gg.rmat(20, ef, 3)
+    pct = 100.0 * np.mean(g.degrees() == 1)
+    assert abs(pct - ref) < 0.5, (pct, ref)
+
+
+def test_table5_counts_are_consistent():
+    t = load("paper_tables.json")
+    n = t["table5_roadnet_pa_vertices"]["value"]
+    assert n - t["table5_h1_skipped"]["value"] == t["table5_h1_skipped"]["remaining"]
+    assert n - t["table5_h2_skipped"]["value"] == t["table5_h2_skipped"]["remaining"]
+
+
+def csr_ok(g):
+    rp, ci = g.row_ptr.astype(np.int64), g.col_idx
+    assert rp[0] == 0 and np.all(np.diff(rp) >= 0) and rp[-1] == len(ci)
+    u = np.repeat(np.arange(g.n), np.diff(rp))
+    assert np.all(ci >= 0) and np.all(ci < g.n)
+    assert not np.any(u == ci)                                  # no self-loops
+    key = u * g.n + ci
+    assert np.all(np.diff(key) > 0)                             # sorted, no duplicates
+    assert np.array_equal(np.sort(ci * g.n + u), key)           # symmetric
+
+
+def test_generators_deterministic_and_valid():
+    a, b = gg.rmat(12, 16, 9), gg.rmat(12, 16, 9)
+    assert np.array_equal(a.row_ptr, b.row_ptr) and np.array_equal(a.col_idx, b.col_idx)
+    c = gg.rmat(12, 16, 10)
+    assert not np.array_equal(a.col_idx[:100], c.col_idx[:100])
+    for g in [a, gg.config_c1(), gg.rmat_with_pendants(12, 16, 3, 0.3, 33), gg.road_grid(64, 48, 0.05, 0.01, 4),
+              gg.hypercube(5), gg.layered_chain(4, 3), gg.random_tree(30, 1), gg.full_grid(5, 7)]:
+        csr_ok(g)
+
+
+def test_road_grid_counts():
+    R, C = 64, 48
+    g = gg.road_grid(R, C, 0.05, 0.01, 4)
+    nl = R * (C - 1) + (R - 1) * C
+    assert g.m == nl - round(0.05 * nl) + round(0.01 * nl)
+    u, v = g.edges()
+    ru, cu, rv, cv = u // C, u % C, v // C, v % C
+    assert np.all(np.abs(ru - rv) + np.abs(cu - cv) <= 2) and np.all(np.abs(ru - rv) <= 1)
+
+
+def test_pendant_recipe():
+    g = gg.rmat_with_pendants(12, 16, 3, 0.3, 33)
+    n0 = 1 << 12
+    P = round(0.3 * n0)
+    assert g.n == n0 + P
+    deg = g.degrees()
+    assert np.all(deg[n0:] == 1)
+    assert np.all(g.col_idx[g.row_ptr[n0:-1]] < n0)
+
+
+def test_sample_without_replacement():
+    cand = np.arange(100, 200, dtype=np.int32)
+    s = gg.sample(cand, 50, 3)
+    assert len(set(s.tolist())) == 50 and set(s.tolist()) <= set(cand.tolist())
+    assert np.array_equal(s, gg.sample(cand, 50, 3))
+
+
+def test_serving_specs_in_range():
+    specs = gg.serving_graph_specs()
+    assert len(specs) == 32
+    assert all(12 <= s <= 20 and ef in (8, 16, 32) for s, ef, _ in specs)
