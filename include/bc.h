@@ -1,0 +1,236 @@
+/*
+ * bc.h -- exact betweenness centrality on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is Brandes' algorithm as restated in Vella, Carbone, Bernaschi,
+ * "Algorithms and Heuristics for Scalable Betweenness Centrality Computation
+ * on Multi-GPU Systems" (arXiv:1602.00963):
+ *   - scores are sums of per-source dependencies (Sec. 2, Eq. (2)-(3));
+ *   - each source runs a level-synchronous shortest-path count (Sec. 3,
+ *     Alg. 2-3) and a successor-checking dependency sweep (Alg. 4-5);
+ *   - optional 1-degree reduction (Sec. 3.5.1, Eq. (4)-(5), Alg. 6) and
+ *     2-degree derivation (Sec. 3.5.2, Lemma 1, Eq. (6), Alg. 7).
+ *
+ * Graphs are simple, undirected and unweighted, given as a symmetric CSR
+ * (row_ptr[n+1], col_idx[nnz], int32, every pair stored in both directions).
+ *
+ * Score convention: RAW scores sum over ordered (source, target) pairs, as
+ * Eq. (3) does; BC_UNDIRECTED halves them (the usual undirected value).
+ *
+ * Ownership: host arrays passed in are only read during the call and are
+ * copied; the library never frees memory it did not allocate.  Device
+ * pointers (BC_LOAD_DEVICE_PTRS, caller workspaces) stay owned by the caller
+ * and must outlive the call (and, for a workspace, the stream work it
+ * enqueued).  Objects are not thread-safe unless stated: use one thread per
+ * bc_graph, or the bc_server API.
+ *
+ * Errors: every function returns a bc_status; no C++ exception crosses this
+ * boundary.  bc_last_error() gives a thread-local message for the last
+ * failure on the calling thread.
+ */
+#ifndef BC_H_
+#define BC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bc_status {
+  BC_OK = 0,
+  BC_E_INVALID_ARG = 1,    /* null pointer, out-of-range id, bad option */
+  BC_E_INVALID_GRAPH = 2,  /* CSR not symmetric/simple/sorted-free, ids out of range, nnz > INT32_MAX */
+  BC_E_OUT_OF_MEMORY = 3,  /* device or host allocation failed, or workspace too small */
+  BC_E_DEVICE = 4,         /* a HIP call failed */
+  BC_E_BUSY = 5,           /* server queue full */
+  BC_E_NOT_FOUND = 6,      /* unknown ticket */
+  BC_E_TIMEOUT = 7,        /* bc_wait timed out; the query is still running */
+  BC_E_REJECTED = 8,       /* query can never fit the server's HBM budget */
+  BC_E_CAPACITY = 9        /* internal list capacity exceeded (retry with a smaller batch) */
+} bc_status;
+
+typedef struct bc_context bc_context;
+typedef struct bc_graph bc_graph;
+typedef struct bc_server bc_server;
+
+/* ------------------------------------------------------------------ context */
+
+/* Binds a HIP device (hipSetDevice on the calling thread) and queries it. */
+bc_status bc_context_create(int device, bc_context** out);
+bc_status bc_context_destroy(bc_context* ctx);
+
+/* ------------------------------------------------------------------- graphs */
+
+enum {
+  BC_LOAD_VALIDATE = 1u,     /* check symmetry, no self-loops, no duplicates, ids in range */
+  BC_LOAD_PRUNE_DEG1 = 2u,   /* build the 1-degree reduction (omega, residual graph), Alg. 6 */
+  BC_LOAD_DEVICE_PTRS = 4u   /* row_ptr / col_idx are device pointers (copied device-to-device) */
+};
+
+typedef struct bc_graph_stats {
+  int64_t n;               /* vertices */
+  int64_t m;               /* unique undirected edges */
+  int64_t nnz;             /* directed CSR entries (= 2m) */
+  int64_t isolated;        /* degree-0 vertices */
+  int64_t pendants;        /* degree-1 vertices removed by the reduction (0 if not pruned) */
+  int64_t k2_vertices;     /* vertices of 2-vertex components (BC = 0, never sources) */
+  int64_t residual_nnz;    /* directed entries of the residual graph G' (= nnz if not pruned) */
+  int64_t deg2_vertices;   /* vertices of degree 2 in the traversed graph */
+  int64_t max_degree;
+  int64_t resident_bytes;  /* device bytes held by the graph (CSR, G', omega, scores) */
+} bc_graph_stats;
+
+/*
+ * Uploads a graph and keeps it resident in HBM.  With BC_LOAD_VALIDATE the
+ * CSR is checked on the host first (BC_E_INVALID_GRAPH, message names the
+ * first offending vertex).  With BC_LOAD_PRUNE_DEG1, degree-1 vertices whose
+ * neighbour has degree >= 2 are folded into omega(neighbour) (Sec. 3.5.1);
+ * both ends of a 2-vertex component are dropped (their score is 0).
+ */
+bc_status bc_graph_load(bc_context* ctx, int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                        int64_t nnz, uint32_t flags, bc_graph** out);
+bc_status bc_graph_stats_get(const bc_graph* g, bc_graph_stats* out);
+bc_status bc_graph_free(bc_graph* g);
+
+/* ------------------------------------------------------------------ compute */
+
+enum {
+  BC_MODE_PLAIN = 0,    /* one cooperative launch per source */
+  BC_MODE_BATCHED = 1   /* one cooperative launch per batch of `batch` sources */
+};
+enum {
+  BC_H_DEG1 = 1u,       /* use the graph's 1-degree reduction (needs BC_LOAD_PRUNE_DEG1) */
+  BC_H_DEG2 = 2u        /* derive 2-degree vertices from their neighbours (batched only) */
+};
+enum {
+  BC_SIGMA_AUTO = 0,    /* exact uint64 counts; sources that wrap are recomputed in extended form */
+  BC_SIGMA_EXACT_ONLY = 1, /* exact uint64; sources that wrap are reported and left out */
+  BC_SIGMA_EXTENDED = 2 /* every source in extended form (fp64 significand + int32 exponent) */
+};
+
+typedef struct bc_compute_opts {
+  int32_t mode;         /* BC_MODE_* */
+  int32_t batch;        /* sources per batch, multiple of 64 in [64, 256]; 0 = 256 */
+  uint32_t heuristics;  /* BC_H_* */
+  int32_t sigma_mode;   /* BC_SIGMA_* */
+  double alpha;         /* bottom-up when frontier edges * alpha > unvisited edges; 0 = default */
+  int32_t block;        /* threads per workgroup (256 or 512); 0 = 256 */
+  int32_t grid_per_cu;  /* workgroups per CU for the persistent grid; 0 = occupancy limit */
+} bc_compute_opts;
+
+typedef struct bc_run_stats {
+  int64_t sources;          /* sources requested (original ids, after dropping isolated) */
+  int64_t traversed;        /* forward sweeps actually run (pruned/derived sources excluded) */
+  int64_t derived;          /* 2-degree sources whose forward sweep was derived */
+  int64_t overflowed;       /* sources whose uint64 count wrapped */
+  int64_t rerun_extended;   /* of those, recomputed in extended form */
+  int32_t first_overflow[8];/* first overflowed source ids (-1 = none) */
+  int64_t levels;           /* sum over launches of forward levels */
+  int64_t bottom_up_levels; /* of which bottom-up */
+  int64_t reached;          /* sum over traversed sources of vertices reached */
+  int64_t reached_nnz;      /* sum of directed CSR entries of reached vertices */
+  int64_t dag_edges;        /* sum of edges joining consecutive levels (directed, parent to child) */
+  int64_t launches;         /* kernel launches */
+  double te;                /* traversed edges credited: sum over requested sources of m (original graph) */
+  double raw_te;            /* traversed sources * m of the traversed graph */
+  double ms;                /* wall time of the call, host-measured, ms */
+} bc_run_stats;
+
+/*
+ * Adds the RAW contributions of the given sources to the graph's score
+ * array (scores accumulate across calls until bc_scores_reset).
+ *   sources: host array of k original vertex ids, or NULL for every
+ *            non-isolated vertex.  Isolated sources contribute nothing.
+ *            With BC_H_DEG1 the graph's pruned vertices are handled
+ *            analytically and never traversed.
+ *   workspace/ws_bytes: device buffer of at least bc_workspace_size()
+ *            bytes, or NULL to use a library-owned cached buffer.
+ *   stream:  hipStream_t to enqueue on (NULL = the null stream).  The call
+ *            blocks until its work is complete.
+ *   stats:   optional.
+ */
+bc_status bc_workspace_size(const bc_graph* g, const bc_compute_opts* opts, size_t* bytes);
+bc_status bc_compute(bc_graph* g, const int32_t* sources, int64_t k, const bc_compute_opts* opts,
+                     void* workspace, size_t ws_bytes, void* stream, bc_run_stats* stats);
+
+enum { BC_RAW = 0, BC_UNDIRECTED = 1 };
+/* Copies the accumulated scores (n doubles) into out (host, or device if
+ * out_on_device != 0), optionally halved. */
+bc_status bc_scores(const bc_graph* g, double* out, int32_t norm, int32_t out_on_device);
+bc_status bc_scores_reset(bc_graph* g);
+
+/*
+ * Parity export.  Runs the given sources (unpruned graph, no scores added)
+ * through the chosen mode and copies per-source results to host arrays laid
+ * out source-major ([i*n + v]): d (-1 unreached), sigma (uint64; for a
+ * source in extended form: 0), sigma_mant/sigma_exp (extended form:
+ * sigma = mant * 2^exp; exact form: mant = (double)sigma, exp = 0), delta
+ * (dependency of v on source i, Eq. (2); 0 at the source and at unreached
+ * vertices), overflow[i].  Any output may be NULL.
+ */
+bc_status bc_trace(bc_graph* g, const int32_t* sources, int64_t k, const bc_compute_opts* opts,
+                   int32_t* d, uint64_t* sigma, double* sigma_mant, int32_t* sigma_exp,
+                   double* delta, int32_t* overflow);
+
+/* -------------------------------------------------------------- host checks */
+
+/* CSR validation only (no device).  Returns BC_OK or BC_E_INVALID_GRAPH. */
+bc_status bc_validate_csr(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int64_t nnz);
+
+/*
+ * The 1-degree reduction on the host (Alg. 6 read as: a vertex u is a
+ * pendant iff deg(u) = 1 and its neighbour has degree >= 2).  Outputs
+ * (caller-allocated): omega[n] (pendants per vertex), kind[n] (0 kept,
+ * 1 pendant, 2 end of a 2-vertex component, 3 isolated), hub[n] (the
+ * neighbour of a pendant, else -1), res_row_ptr[n+1], res_col_idx[nnz]
+ * (the residual graph G' on the same ids; pruned vertices get empty rows).
+ * *res_nnz receives the residual entry count.
+ */
+bc_status bc_prune_deg1_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                             int32_t* omega, int32_t* kind, int32_t* hub,
+                             int32_t* res_row_ptr, int32_t* res_col_idx, int64_t* res_nnz);
+
+/* ------------------------------------------------------------------ serving */
+
+typedef struct bc_server_config {
+  int64_t hbm_budget_bytes;  /* workspace bytes the server may hold at once; 0 = 64 GiB */
+  int32_t max_inflight;      /* concurrent batches (streams); 0 = 4 */
+  int32_t batch;             /* sources per batch; 0 = 256 */
+  int32_t queue_capacity;    /* pending queries; 0 = 4096 */
+} bc_server_config;
+
+typedef struct bc_query_stats {
+  double submit_ms, start_ms, end_ms;  /* host clock, ms since server creation */
+  double latency_ms;                   /* end - submit */
+  int64_t sources;                     /* sources of the query */
+  double te;                           /* sources * m */
+  int32_t status;                      /* bc_status of the query */
+} bc_query_stats;
+
+/*
+ * Continuous-batching server.  Queries (graph, source subset) are admitted
+ * by the HBM footprint of the batches they need; sources of queries on the
+ * same graph share batches; up to max_inflight batches run concurrently on
+ * their own streams.  Each query's RAW scores are written into its `out`
+ * array (n doubles, host), which must stay valid until bc_wait returns for
+ * its ticket.  A query's result does not depend on which other queries share
+ * its batches beyond floating-point summation order (relative 1e-9).
+ * The server API is thread-safe.
+ */
+bc_status bc_server_create(bc_context* ctx, const bc_server_config* cfg, bc_server** out);
+bc_status bc_server_destroy(bc_server* s);
+bc_status bc_submit(bc_server* s, bc_graph* g, const int32_t* sources, int64_t k, double* out,
+                    uint64_t* ticket);
+bc_status bc_wait(bc_server* s, uint64_t ticket, int64_t timeout_us, bc_query_stats* stats);
+
+/* ------------------------------------------------------------------- errors */
+
+const char* bc_status_string(bc_status st);
+const char* bc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BC_H_ */

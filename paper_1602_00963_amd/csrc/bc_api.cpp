@@ -1,0 +1,1071 @@
+// C ABI of the library: graph residency, workspace layout, the plain and
+// batched drivers, parity traces and host-side checks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bc.h"
+#include "bc_api_internal.h"
+#include "bc_host.h"
+#include "bc_kernels.h"
+
+using namespace bcx;
+
+static thread_local std::string g_err;
+
+bc_status bcx::fail(bc_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(x)                                                                             \
+  do {                                                                                        \
+    hipError_t e_ = (x);                                                                      \
+    if (e_ != hipSuccess) return fail(BC_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Sequential carving of a workspace; with base == nullptr it only sizes.
+struct Carve {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+constexpr int kTableBatches = 256;  // lane tables uploaded per group of batches
+
+int64_t plain_cap_units(int64_t n, int64_t nnz) { return n + nnz / kPlainChunkHost + 64; }
+int64_t plain_cap_parts(int64_t n, int64_t nnz) { return n + nnz / kPlainChunkHost + 64; }
+
+struct PlainWs {
+  int32_t *d, *se, *Q, *qoff, *uoff, *part_e, *arrive, *gmulti, *err, *ovf_now, *ovf_list, *ovf_count;
+  uint64_t *sig, *ns;
+  double *sm, *psi, *part_m, *delta, *bc_tmp;
+  Unit* U;
+  LevelCtr* lc;
+  unsigned long long* stats;
+  size_t ctl_bytes;  // bytes from `lc` through the control scalars (zeroed per call)
+  char* ctl_begin;
+};
+
+size_t plain_layout(int64_t n, int64_t nnz, char* base, PlainWs* w) {
+  Carve c{base};
+  PlainWs t{};
+  t.d = c.take<int32_t>(n);
+  t.sig = c.take<uint64_t>(n);
+  t.sm = c.take<double>(n);
+  t.se = c.take<int32_t>(n);
+  t.psi = c.take<double>(n);
+  t.Q = c.take<int32_t>(n);
+  t.U = c.take<Unit>(plain_cap_units(n, nnz));
+  t.qoff = c.take<int32_t>(n + 3);
+  t.uoff = c.take<int32_t>(n + 3);
+  t.part_m = c.take<double>(plain_cap_parts(n, nnz));
+  t.part_e = c.take<int32_t>(plain_cap_parts(n, nnz));
+  t.arrive = c.take<int32_t>(n);
+  t.ovf_list = c.take<int32_t>(n + 1);
+  t.delta = c.take<double>(n);
+  t.bc_tmp = c.take<double>(n);
+  c.off = align_up(c.off, 256);
+  const size_t ctl0 = c.off;
+  t.lc = c.take<LevelCtr>(n + 3);
+  t.gmulti = c.take<int32_t>(1);
+  t.err = c.take<int32_t>(1);
+  t.ovf_now = c.take<int32_t>(1);
+  t.ovf_count = c.take<int32_t>(1);
+  t.ns = c.take<uint64_t>(1);
+  t.stats = c.take<unsigned long long>(kStCount);
+  c.off = align_up(c.off, 256);
+  t.ctl_bytes = c.off - ctl0;
+  t.ctl_begin = base ? base + ctl0 : nullptr;
+  if (w) *w = t;
+  return c.off;
+}
+
+struct BatchCaps {
+  int64_t entries, units, parts, multi;
+};
+
+BatchCaps batch_caps(int64_t n, int64_t nnz, int B, int cap_factor) {
+  const int64_t f = std::min<int64_t>(B, cap_factor);
+  BatchCaps c;
+  c.entries = std::min<int64_t>((int64_t)n * f + 1024, (int64_t)INT32_MAX / 2);
+  c.units = std::min<int64_t>(c.entries + nnz * f / kBatchChunk + 1024, (int64_t)INT32_MAX / 2);
+  c.parts = 2 * nnz / kBatchChunk + 1024;
+  c.multi = c.entries;
+  return c;
+}
+
+struct BatchWs {
+  int32_t *lv, *se, *stamp, *Q, *qoff, *uoff, *part_e, *arrive, *gmulti, *err, *ovf_list, *ovf_count;
+  int32_t *fail_list, *fail_count;
+  uint64_t *sig, *vis, *fm;
+  double *part_m;
+  Unit* U;
+  LevelCtr* lc;
+  uint32_t* lane_ovf;
+  unsigned long long *lane_ns, *stats, *fulledges;
+  char* tables;        // kTableBatches lane tables
+  size_t table_bytes;  // bytes of one table
+  size_t ctl_bytes;
+  char* ctl_begin;
+  BatchCaps caps;
+};
+
+// One batch's lane table: lane_src[B], lane_own[B], l0[B] (int32), lane_w[B]
+// (double), lane_pa[B], lane_pb[B], lane_slot[B] (int8), then 8-aligned
+// edge_lanes[4] (uint64) and slot_bc[64] (device pointers).
+constexpr int kMaxSlots = 64;
+size_t table_bytes(int B) {
+  return align_up((size_t)B * (4 + 4 + 4 + 8 + 1 + 1 + 1) + 8 + 8 * 4 + 8 * kMaxSlots, 256);
+}
+
+size_t batch_layout(int64_t n, int64_t nnz, int B, int cap_factor, char* base, BatchWs* w) {
+  const int K = B / 64;
+  Carve c{base};
+  BatchWs t{};
+  t.caps = batch_caps(n, nnz, B, cap_factor);
+  t.lv = c.take<int32_t>((size_t)n * B);
+  t.sig = c.take<uint64_t>((size_t)n * B);
+  t.se = c.take<int32_t>((size_t)n * B);
+  t.vis = c.take<uint64_t>((size_t)n * K);
+  t.fm = c.take<uint64_t>((size_t)3 * n * K);
+  t.stamp = c.take<int32_t>(n);
+  t.Q = c.take<int32_t>(t.caps.entries);
+  t.U = c.take<Unit>(t.caps.units);
+  t.qoff = c.take<int32_t>(n + 3);
+  t.uoff = c.take<int32_t>(n + 3);
+  t.part_m = c.take<double>((size_t)t.caps.parts * K * 64);
+  t.part_e = c.take<int32_t>((size_t)t.caps.parts * K * 64);
+  t.arrive = c.take<int32_t>(t.caps.multi);
+  t.ovf_list = c.take<int32_t>(n + 1);
+  t.fail_list = c.take<int32_t>(n + 1);
+  t.table_bytes = table_bytes(B);
+  t.tables = c.take<char>(t.table_bytes * kTableBatches);
+  c.off = align_up(c.off, 256);
+  const size_t ctl0 = c.off;
+  t.lc = c.take<LevelCtr>(n + 3);
+  t.gmulti = c.take<int32_t>(1);
+  t.err = c.take<int32_t>(1);
+  t.ovf_count = c.take<int32_t>(1);
+  t.fail_count = c.take<int32_t>(1);
+  t.lane_ovf = c.take<uint32_t>(B);
+  t.lane_ns = c.take<unsigned long long>(B);
+  t.fulledges = c.take<unsigned long long>(1);
+  t.stats = c.take<unsigned long long>(kStCount);
+  c.off = align_up(c.off, 256);
+  t.ctl_bytes = c.off - ctl0;
+  t.ctl_begin = base ? base + ctl0 : nullptr;
+  if (w) *w = t;
+  return c.off;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ objects
+
+struct bc_context {
+  int device = 0;
+  int cus = 0;
+  std::string arch;
+};
+
+struct bc_graph {
+  bc_context* ctx = nullptr;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  bool pruned = false;
+  std::vector<int32_t> h_rp, h_ci;  // original graph (host copy)
+  Pruned pr;
+  // device: original graph and (if pruned) the residual graph G'
+  int32_t *d_rp = nullptr, *d_ci = nullptr, *d_rrp = nullptr, *d_rci = nullptr, *d_omega = nullptr;
+  int2 *d_gu_p = nullptr, *d_gu_b = nullptr, *d_rgu_p = nullptr, *d_rgu_b = nullptr;
+  int32_t ngu_p = 0, ngu_b = 0, nrgu_p = 0, nrgu_b = 0;
+  double* d_bc = nullptr;
+  int64_t resident = 0;
+  int64_t max_degree = 0, isolated = 0, pendants = 0, k2 = 0, deg2 = 0, rnnz = 0;
+  // library-owned cached workspace
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::mutex mu;
+};
+
+namespace bcx {
+
+// Static units (vertex, chunk) of every vertex with edges.
+static std::vector<int2> static_units(int32_t n, const int32_t* rp, int chunk) {
+  std::vector<int2> u;
+  for (int32_t v = 0; v < n; ++v) {
+    const int32_t dg = rp[v + 1] - rp[v];
+    if (dg == 0) continue;
+    const int32_t nu = (dg + chunk - 1) / chunk;
+    for (int32_t c = 0; c < nu; ++c) u.push_back(make_int2(v, c));
+  }
+  return u;
+}
+
+template <class T>
+static bc_status upload(const std::vector<T>& h, T** d, int64_t* resident) {
+  const size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
+  HIPCHK(hipMalloc((void**)d, bytes));
+  if (!h.empty()) HIPCHK(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *resident += (int64_t)bytes;
+  return BC_OK;
+}
+
+}  // namespace bcx
+
+extern "C" {
+
+const char* bc_status_string(bc_status st) {
+  switch (st) {
+    case BC_OK: return "ok";
+    case BC_E_INVALID_ARG: return "invalid argument";
+    case BC_E_INVALID_GRAPH: return "invalid graph";
+    case BC_E_OUT_OF_MEMORY: return "out of memory";
+    case BC_E_DEVICE: return "device error";
+    case BC_E_BUSY: return "busy";
+    case BC_E_NOT_FOUND: return "not found";
+    case BC_E_TIMEOUT: return "timeout";
+    case BC_E_REJECTED: return "rejected";
+    case BC_E_CAPACITY: return "capacity exceeded";
+  }
+  return "unknown status";
+}
+
+const char* bc_last_error(void) { return g_err.c_str(); }
+
+bc_status bc_context_create(int device, bc_context** out) {
+  if (!out) return fail(BC_E_INVALID_ARG, "out is null");
+  int count = 0;
+  HIPCHK(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(BC_E_INVALID_ARG, "device id out of range");
+  HIPCHK(hipSetDevice(device));
+  hipDeviceProp_t p;
+  HIPCHK(hipGetDeviceProperties(&p, device));
+  auto* c = new bc_context;
+  c->device = device;
+  c->cus = p.multiProcessorCount;
+  c->arch = p.gcnArchName;
+  *out = c;
+  return BC_OK;
+}
+
+bc_status bc_context_destroy(bc_context* ctx) {
+  delete ctx;
+  return BC_OK;
+}
+
+bc_status bc_validate_csr(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int64_t nnz) {
+  if (!row_ptr || (nnz > 0 && !col_idx)) return fail(BC_E_INVALID_ARG, "null CSR array");
+  std::string why;
+  if (!validate_csr(n, row_ptr, col_idx, nnz, &why)) return fail(BC_E_INVALID_GRAPH, why);
+  return BC_OK;
+}
+
+bc_status bc_prune_deg1_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t* omega,
+                             int32_t* kind, int32_t* hub, int32_t* res_row_ptr, int32_t* res_col_idx,
+                             int64_t* res_nnz) {
+  if (!row_ptr || !col_idx || n < 0) return fail(BC_E_INVALID_ARG, "null CSR array");
+  Pruned p;
+  prune_deg1(n, row_ptr, col_idx, &p);
+  if (omega) memcpy(omega, p.omega.data(), sizeof(int32_t) * n);
+  if (kind) memcpy(kind, p.kind.data(), sizeof(int32_t) * n);
+  if (hub) memcpy(hub, p.hub.data(), sizeof(int32_t) * n);
+  if (res_row_ptr) memcpy(res_row_ptr, p.rp.data(), sizeof(int32_t) * (n + 1));
+  if (res_col_idx) memcpy(res_col_idx, p.ci.data(), sizeof(int32_t) * p.ci.size());
+  if (res_nnz) *res_nnz = (int64_t)p.ci.size();
+  return BC_OK;
+}
+
+bc_status bc_graph_load(bc_context* ctx, int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
+                        int64_t nnz, uint32_t flags, bc_graph** out) {
+  if (!ctx || !out || n <= 0 || !row_ptr || (nnz > 0 && !col_idx)) return fail(BC_E_INVALID_ARG, "bad arguments");
+  if (nnz < 0 || nnz > INT32_MAX) return fail(BC_E_INVALID_GRAPH, "nnz must fit int32");
+  HIPCHK(hipSetDevice(ctx->device));
+  auto g = new bc_graph;
+  g->ctx = ctx;
+  g->n = n;
+  g->nnz = nnz;
+  g->h_rp.resize((size_t)n + 1);
+  g->h_ci.resize((size_t)nnz);
+  if (flags & BC_LOAD_DEVICE_PTRS) {
+    if (hipMemcpy(g->h_rp.data(), row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost) != hipSuccess ||
+        (nnz && hipMemcpy(g->h_ci.data(), col_idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost) != hipSuccess)) {
+      delete g;
+      return fail(BC_E_DEVICE, "copy of device CSR failed");
+    }
+  } else {
+    memcpy(g->h_rp.data(), row_ptr, sizeof(int32_t) * (n + 1));
+    if (nnz) memcpy(g->h_ci.data(), col_idx, sizeof(int32_t) * nnz);
+  }
+  const int32_t* rp = g->h_rp.data();
+  const int32_t* ci = g->h_ci.data();
+  if (flags & BC_LOAD_VALIDATE) {
+    std::string why;
+    if (!validate_csr(n, rp, ci, nnz, &why)) { delete g; return fail(BC_E_INVALID_GRAPH, why); }
+  } else if (rp[0] != 0 || rp[n] != nnz) {
+    delete g;
+    return fail(BC_E_INVALID_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    const int64_t dg = rp[v + 1] - rp[v];
+    g->max_degree = std::max(g->max_degree, dg);
+    g->isolated += dg == 0;
+  }
+  bc_status st = BC_OK;
+  st = upload(g->h_rp, &g->d_rp, &g->resident);
+  if (st == BC_OK) st = upload(g->h_ci, &g->d_ci, &g->resident);
+  if (st == BC_OK) {
+    auto up = static_units(n, rp, kPlainChunkHost), ub = static_units(n, rp, kBatchChunk);
+    g->ngu_p = (int32_t)up.size();
+    g->ngu_b = (int32_t)ub.size();
+    st = upload(up, &g->d_gu_p, &g->resident);
+    if (st == BC_OK) st = upload(ub, &g->d_gu_b, &g->resident);
+  }
+  const int32_t* trp = rp;
+  if (st == BC_OK && (flags & BC_LOAD_PRUNE_DEG1)) {
+    g->pruned = true;
+    prune_deg1(n, rp, ci, &g->pr);
+    for (int32_t v = 0; v < n; ++v) {
+      g->pendants += g->pr.kind[v] == kPendant;
+      g->k2 += g->pr.kind[v] == kK2;
+    }
+    g->rnnz = (int64_t)g->pr.ci.size();
+    st = upload(g->pr.rp, &g->d_rrp, &g->resident);
+    if (st == BC_OK) st = upload(g->pr.ci, &g->d_rci, &g->resident);
+    if (st == BC_OK) st = upload(g->pr.omega, &g->d_omega, &g->resident);
+    if (st == BC_OK) {
+      auto up = static_units(n, g->pr.rp.data(), kPlainChunkHost), ub = static_units(n, g->pr.rp.data(), kBatchChunk);
+      g->nrgu_p = (int32_t)up.size();
+      g->nrgu_b = (int32_t)ub.size();
+      st = upload(up, &g->d_rgu_p, &g->resident);
+      if (st == BC_OK) st = upload(ub, &g->d_rgu_b, &g->resident);
+    }
+    trp = g->pr.rp.data();
+  } else {
+    g->rnnz = nnz;
+  }
+  for (int32_t v = 0; v < n; ++v) g->deg2 += (trp[v + 1] - trp[v]) == 2;
+  if (st == BC_OK) {
+    if (hipMalloc((void**)&g->d_bc, sizeof(double) * n) != hipSuccess) st = fail(BC_E_OUT_OF_MEMORY, "score array");
+    else if (hipMemset(g->d_bc, 0, sizeof(double) * n) != hipSuccess) st = fail(BC_E_DEVICE, "memset");
+    g->resident += (int64_t)sizeof(double) * n;
+  }
+  if (st != BC_OK) {
+    bc_graph_free(g);
+    return st;
+  }
+  *out = g;
+  return BC_OK;
+}
+
+bc_status bc_graph_stats_get(const bc_graph* g, bc_graph_stats* out) {
+  if (!g || !out) return fail(BC_E_INVALID_ARG, "null argument");
+  out->n = g->n;
+  out->nnz = g->nnz;
+  out->m = g->nnz / 2;
+  out->isolated = g->isolated;
+  out->pendants = g->pendants;
+  out->k2_vertices = g->k2;
+  out->residual_nnz = g->rnnz;
+  out->deg2_vertices = g->deg2;
+  out->max_degree = g->max_degree;
+  out->resident_bytes = g->resident;
+  return BC_OK;
+}
+
+bc_status bc_graph_free(bc_graph* g) {
+  if (!g) return BC_OK;
+  (void)hipSetDevice(g->ctx->device);
+  for (void* p : {(void*)g->d_rp, (void*)g->d_ci, (void*)g->d_rrp, (void*)g->d_rci, (void*)g->d_omega,
+                  (void*)g->d_gu_p, (void*)g->d_gu_b, (void*)g->d_rgu_p, (void*)g->d_rgu_b, (void*)g->d_bc, g->ws})
+    if (p) (void)hipFree(p);
+  delete g;
+  return BC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- compute
+
+namespace bcx {
+
+static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* r) {
+  bc_compute_opts d{};
+  if (!o) o = &d;
+  r->mode = o->mode;
+  if (r->mode != BC_MODE_PLAIN && r->mode != BC_MODE_BATCHED) return fail(BC_E_INVALID_ARG, "unknown mode");
+  r->B = o->batch ? o->batch : 256;
+  if (r->B % 64 != 0 || r->B < 64 || r->B > 256) return fail(BC_E_INVALID_ARG, "batch must be 64, 128, 192 or 256");
+  r->K = r->B / 64;
+  r->block = o->block ? o->block : 256;
+  if (r->block != 256) return fail(BC_E_INVALID_ARG, "block must be 256");
+  r->grid_per_cu = o->grid_per_cu;
+  r->sigma_mode = o->sigma_mode;
+  if (r->sigma_mode < 0 || r->sigma_mode > 2) return fail(BC_E_INVALID_ARG, "unknown sigma mode");
+  r->deg1 = (o->heuristics & BC_H_DEG1) != 0;
+  r->deg2 = (o->heuristics & BC_H_DEG2) != 0;
+  if (r->deg1 && !g->pruned) return fail(BC_E_INVALID_ARG, "BC_H_DEG1 needs a graph loaded with BC_LOAD_PRUNE_DEG1");
+  if (r->deg2 && r->mode != BC_MODE_BATCHED) return fail(BC_E_INVALID_ARG, "BC_H_DEG2 needs the batched mode");
+  r->alpha = o->alpha > 0 ? o->alpha : (r->mode == BC_MODE_PLAIN ? 4.0 : 2.0);
+  return BC_OK;
+}
+
+size_t ws_bytes_for(const bc_graph* g, const Resolved& r, int cap_factor) {
+  if (r.mode == BC_MODE_PLAIN) return plain_layout(g->n, g->nnz, nullptr, nullptr);
+  return batch_layout(g->n, g->nnz, r.B, cap_factor, nullptr, nullptr);
+}
+
+struct TravGraph {
+  const int32_t *rp, *ci, *omega;
+  const int2 *gu_p, *gu_b;
+  int32_t ngu_p, ngu_b;
+  int64_t nnz;
+  const int32_t* h_rp;
+  const int32_t* h_ci;
+};
+
+static TravGraph trav(const bc_graph* g, bool deg1) {
+  if (deg1)
+    return TravGraph{g->d_rrp, g->d_rci, g->d_omega, g->d_rgu_p, g->d_rgu_b, g->nrgu_p, g->nrgu_b,
+                     (int64_t)g->pr.ci.size(), g->pr.rp.data(), g->pr.ci.data()};
+  return TravGraph{g->d_rp, g->d_ci, nullptr, g->d_gu_p, g->d_gu_b, g->ngu_p, g->ngu_b, g->nnz,
+                   g->h_rp.data(), g->h_ci.data()};
+}
+
+static int grid_for(const bc_graph* g, const Resolved& r, bool ext, bool batched) {
+  int bpc = 1;
+  hipError_t e = batched ? batch_max_grid(ext, r.K, r.block, &bpc) : plain_max_grid(ext, r.block, &bpc);
+  if (e != hipSuccess || bpc < 1) bpc = 1;
+  int want = r.grid_per_cu > 0 ? r.grid_per_cu : (batched ? bpc : 1);
+  return g->ctx->cus * std::min(want, bpc);
+}
+
+// Lane packing of one call: a list of batches, each with per-lane group
+// indices (-1 = empty) and derived-lane partners.
+struct Packing {
+  int B;
+  std::vector<int32_t> lane_group;  // nbatches * B
+  std::vector<int8_t> pa, pb;       // nbatches * B
+  int64_t nbatches = 0;
+  int64_t derived = 0;
+};
+
+static void pack_lanes(const std::vector<Group>& groups, const std::vector<Triple>& triples, int B, Packing* p) {
+  p->B = B;
+  std::vector<char> in_triple(groups.size(), 0);
+  for (const auto& t : triples) in_triple[t.a] = in_triple[t.b] = in_triple[t.c] = 1;
+  std::vector<int32_t> lanes;
+  std::vector<int8_t> pa, pb;
+  auto pad_to_word = [&](int need) {
+    const size_t used = lanes.size() % 64;
+    if (used + need > 64) {
+      while (lanes.size() % 64) { lanes.push_back(-1); pa.push_back(-1); pb.push_back(-1); }
+    }
+  };
+  for (const auto& t : triples) {
+    pad_to_word(3);
+    const int base = (int)(lanes.size() % 64);
+    lanes.push_back(t.a); pa.push_back(-1); pb.push_back(-1);
+    lanes.push_back(t.b); pa.push_back(-1); pb.push_back(-1);
+    lanes.push_back(t.c); pa.push_back((int8_t)base); pb.push_back((int8_t)(base + 1));
+  }
+  for (size_t i = 0; i < groups.size(); ++i) {
+    if (in_triple[i]) continue;
+    lanes.push_back((int32_t)i); pa.push_back(-1); pb.push_back(-1);
+  }
+  while (lanes.size() % B) { lanes.push_back(-1); pa.push_back(-1); pb.push_back(-1); }
+  p->lane_group = std::move(lanes);
+  p->pa = std::move(pa);
+  p->pb = std::move(pb);
+  p->nbatches = (int64_t)(p->lane_group.size() / B);
+  p->derived = (int64_t)triples.size();
+}
+
+struct TablePtrs {
+  int32_t *lane_src, *lane_own, *l0;
+  double* lane_w;
+  int8_t *pa, *pb, *slot;
+  uint64_t* el;
+  double** slot_bc;
+};
+
+static TablePtrs table_at(char* t, int B) {
+  TablePtrs p;
+  p.lane_src = (int32_t*)t;
+  p.lane_own = p.lane_src + B;
+  p.l0 = p.lane_own + B;
+  p.lane_w = (double*)(p.l0 + B);
+  p.pa = (int8_t*)(p.lane_w + B);
+  p.pb = p.pa + B;
+  p.slot = p.pb + B;
+  p.el = (uint64_t*)(((uintptr_t)(p.slot + B) + 7) & ~(uintptr_t)7);
+  p.slot_bc = (double**)(p.el + 4);
+  return p;
+}
+
+// Fills one batch's table; returns the number of distinct source vertices.
+static int32_t fill_table(char* dst, const Packing& pk, int64_t b, const std::vector<Group>& groups, int B,
+                          double* const* slot_ptrs, int nslots) {
+  TablePtrs t = table_at(dst, B);
+  for (int k = 0; k < 4; ++k) t.el[k] = 0;
+  for (int s = 0; s < kMaxSlots; ++s) t.slot_bc[s] = s < nslots ? slot_ptrs[s] : nullptr;
+  std::vector<int32_t> distinct;
+  for (int j = 0; j < B; ++j) {
+    const int32_t gi = pk.lane_group[(size_t)b * B + j];
+    t.pa[j] = pk.pa[(size_t)b * B + j];
+    t.pb[j] = pk.pb[(size_t)b * B + j];
+    t.slot[j] = 0;
+    if (gi < 0) { t.lane_src[j] = -1; t.lane_own[j] = 0; t.lane_w[j] = 0.0; continue; }
+    t.lane_src[j] = groups[gi].v;
+    t.lane_own[j] = groups[gi].own;
+    t.lane_w[j] = groups[gi].w;
+    t.slot[j] = (int8_t)groups[gi].slot;
+    distinct.push_back(groups[gi].v);
+    if (t.pa[j] < 0) t.el[j >> 6] |= 1ull << (j & 63);
+  }
+  std::sort(distinct.begin(), distinct.end());
+  distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+  for (int j = 0; j < B; ++j) t.l0[j] = j < (int)distinct.size() ? distinct[j] : -1;
+  return (int32_t)distinct.size();
+}
+
+static void table_ptrs(char* dev, int B, BatchArgs* a) {
+  TablePtrs t = table_at(dev, B);
+  a->lane_src = t.lane_src;
+  a->lane_own = t.lane_own;
+  a->l0 = t.l0;
+  a->lane_w = t.lane_w;
+  a->lane_pa = t.pa;
+  a->lane_pb = t.pb;
+  a->lane_slot = t.slot;
+  a->edge_lanes = t.el;
+  a->slot_bc = t.slot_bc;
+}
+
+struct CallOut {
+  std::vector<int32_t> ovf;   // overflowed traversal sources
+  std::vector<int32_t> fail;  // sources of batches that exceeded a list capacity
+  unsigned long long st[kStCount] = {0};
+  int err = 0;
+};
+
+// Trace destinations (device) for a batch, or nulls.
+struct TraceDev {
+  double* delta = nullptr;
+  uint64_t* sig = nullptr;
+  double* sm = nullptr;
+  int32_t* se = nullptr;
+  double* bc = nullptr;  // scratch score array
+};
+
+// Pinned staging for lane tables, one per host thread (the serving loop runs
+// batches from several threads at once).
+struct PinnedStage {
+  char* p = nullptr;
+  size_t bytes = 0;
+  ~PinnedStage() { if (p) (void)hipHostFree(p); }
+};
+static thread_local PinnedStage t_stage;
+
+static bc_status ensure_tables(size_t bytes, char** out) {
+  if (t_stage.bytes < bytes) {
+    if (t_stage.p) (void)hipHostFree(t_stage.p);
+    t_stage.p = nullptr;
+    t_stage.bytes = 0;
+    HIPCHK(hipHostMalloc((void**)&t_stage.p, bytes, hipHostMallocDefault));
+    t_stage.bytes = bytes;
+  }
+  *out = t_stage.p;
+  return BC_OK;
+}
+
+// Runs all groups through the batched kernel.  Scores go to `bc`.
+bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg,
+                      const std::vector<Group>& groups, const std::vector<Triple>& triples, char* wsbase,
+                      int cap_factor, hipStream_t st, double* const* slot_ptrs, int nslots, const TraceDev* tr,
+                      CallOut* out, std::vector<int32_t>* trace_lane_vertex) {
+  BatchWs w;
+  batch_layout(g->n, g->nnz, r.B, cap_factor, wsbase, &w);
+  HIPCHK(hipMemsetAsync(w.ctl_begin, 0, w.ctl_bytes, st));
+  Packing pk;
+  pack_lanes(groups, triples, r.B, &pk);
+  if (trace_lane_vertex) trace_lane_vertex->assign(pk.lane_group.begin(), pk.lane_group.end());
+  char* stage = nullptr;
+  bc_status s = ensure_tables(w.table_bytes * kTableBatches, &stage);
+  if (s != BC_OK) return s;
+  const int grid = grid_for(g, r, ext, true);
+  BatchArgs a{};
+  a.n = g->n;
+  a.nnz = tg.nnz;
+  a.K = r.K;
+  a.rp = tg.rp;
+  a.ci = tg.ci;
+  a.omega = tg.omega;
+  a.gu = tg.gu_b;
+  a.ngu = tg.ngu_b;
+  a.lv = w.lv;
+  a.sig = w.sig;
+  a.sm = (double*)w.sig;
+  a.se = w.se;
+  a.vis = w.vis;
+  a.fm = w.fm;
+  a.stamp = w.stamp;
+  a.Q = w.Q;
+  a.U = w.U;
+  a.qoff = w.qoff;
+  a.uoff = w.uoff;
+  a.lc = w.lc;
+  a.part_m = w.part_m;
+  a.part_e = w.part_e;
+  a.arrive = w.arrive;
+  a.gmulti = w.gmulti;
+  a.err = w.err;
+  a.lane_ovf = w.lane_ovf;
+  a.ovf_list = w.ovf_list;
+  a.ovf_count = w.ovf_count;
+  a.lane_ns = w.lane_ns;
+  a.stats = w.stats;
+  a.fail_list = w.fail_list;
+  a.fail_count = w.fail_count;
+  a.fulledges = w.fulledges;
+  a.alpha = r.alpha;
+  a.cap_entries = (int32_t)w.caps.entries;
+  a.cap_units = (int32_t)w.caps.units;
+  a.cap_parts = (int32_t)w.caps.parts;
+  a.cap_multi = (int32_t)w.caps.multi;
+  a.cap_levels = g->n + 3;
+  bool any_own = false;
+  for (const auto& gr : groups) any_own |= gr.own > 0;
+  a.has_own = any_own ? 1 : 0;
+  for (int64_t b0 = 0; b0 < pk.nbatches; b0 += kTableBatches) {
+    const int64_t nb = std::min<int64_t>(kTableBatches, pk.nbatches - b0);
+    std::vector<int32_t> nl0(nb);
+    for (int64_t b = 0; b < nb; ++b)
+      nl0[b] = fill_table(stage + b * w.table_bytes, pk, b0 + b, groups, r.B, slot_ptrs, nslots);
+    HIPCHK(hipMemcpyAsync(w.tables, stage, nb * w.table_bytes, hipMemcpyHostToDevice, st));
+    for (int64_t b = 0; b < nb; ++b) {
+      char* t = w.tables + b * w.table_bytes;
+      table_ptrs(t, r.B, &a);
+      a.nl0 = nl0[b];
+      bool hd = false;
+      for (int j = 0; j < r.B; ++j) hd |= pk.pa[(size_t)(b0 + b) * r.B + j] >= 0;
+      a.has_derived = hd ? 1 : 0;
+      if (tr) {
+        const size_t off = (size_t)b * r.B * g->n;
+        a.delta_out = tr->delta ? tr->delta + off : nullptr;
+        a.sig_out = (!ext && tr->sig) ? tr->sig + off : nullptr;
+        a.sm_out = (ext && tr->sm) ? tr->sm + off : nullptr;
+        a.se_out = (ext && tr->se) ? tr->se + off : nullptr;
+      }
+      HIPCHK(launch_batch(a, ext, grid, r.block, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));  // staging buffer reused by the next group
+  }
+  int32_t cnt = 0, err = 0, fcnt = 0;
+  HIPCHK(hipMemcpyAsync(&cnt, w.ovf_count, sizeof cnt, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&fcnt, w.fail_count, sizeof fcnt, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&err, w.err, sizeof err, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(out->st, w.stats, sizeof(out->st), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  out->err = err;
+  out->ovf.resize(std::min<int32_t>(cnt, g->n + 1));
+  out->fail.resize(std::min<int32_t>(fcnt, g->n + 1));
+  if (!out->ovf.empty())
+    HIPCHK(hipMemcpy(out->ovf.data(), w.ovf_list, sizeof(int32_t) * out->ovf.size(), hipMemcpyDeviceToHost));
+  if (!out->fail.empty())
+    HIPCHK(hipMemcpy(out->fail.data(), w.fail_list, sizeof(int32_t) * out->fail.size(), hipMemcpyDeviceToHost));
+  return BC_OK;
+}
+
+bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg, const std::vector<Group>& groups,
+                    char* wsbase, hipStream_t st, double* bc, double* delta_out, CallOut* out) {
+  PlainWs w;
+  plain_layout(g->n, g->nnz, wsbase, &w);
+  HIPCHK(hipMemsetAsync(w.ctl_begin, 0, w.ctl_bytes, st));
+  const int grid = grid_for(g, r, ext, false);
+  PlainArgs a{};
+  a.n = g->n;
+  a.nnz = tg.nnz;
+  a.rp = tg.rp;
+  a.ci = tg.ci;
+  a.omega = tg.omega;
+  a.gu = tg.gu_p;
+  a.ngu = tg.ngu_p;
+  a.d = w.d;
+  a.sig = w.sig;
+  a.sm = w.sm;
+  a.se = w.se;
+  a.psi = w.psi;
+  a.Q = w.Q;
+  a.U = w.U;
+  a.qoff = w.qoff;
+  a.uoff = w.uoff;
+  a.lc = w.lc;
+  a.part_m = w.part_m;
+  a.part_e = w.part_e;
+  a.arrive = w.arrive;
+  a.gmulti = w.gmulti;
+  a.err = w.err;
+  a.ovf_now = w.ovf_now;
+  a.ovf_list = w.ovf_list;
+  a.ovf_count = w.ovf_count;
+  a.ns = w.ns;
+  a.stats = w.stats;
+  a.bc = bc;
+  a.delta_out = delta_out;
+  a.alpha = r.alpha;
+  a.cap_entries = g->n;
+  a.cap_units = (int32_t)plain_cap_units(g->n, g->nnz);
+  a.cap_parts = (int32_t)plain_cap_parts(g->n, g->nnz);
+  a.cap_multi = g->n;
+  a.cap_levels = g->n + 3;
+  for (const auto& gr : groups) {
+    a.src = gr.v;
+    a.weight = gr.w;
+    a.own = gr.own;
+    HIPCHK(launch_plain(a, ext, grid, r.block, st));
+  }
+  int32_t cnt = 0, err = 0;
+  HIPCHK(hipMemcpyAsync(&cnt, w.ovf_count, sizeof cnt, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&err, w.err, sizeof err, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(out->st, w.stats, sizeof(out->st), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  out->err = err;
+  out->ovf.resize(std::min<int32_t>(cnt, g->n + 1));
+  if (cnt) HIPCHK(hipMemcpy(out->ovf.data(), w.ovf_list, sizeof(int32_t) * out->ovf.size(), hipMemcpyDeviceToHost));
+  return BC_OK;
+}
+
+static void add_stats(bc_run_stats* s, const CallOut& o) {
+  s->levels += (int64_t)o.st[kStLevels];
+  s->bottom_up_levels += (int64_t)o.st[kStBuLevels];
+  s->reached += (int64_t)o.st[kStReached];
+  s->reached_nnz += (int64_t)o.st[kStReachedNnz];
+  s->dag_edges += (int64_t)o.st[kStDag];
+  s->launches += (int64_t)o.st[kStLaunches];
+}
+
+// Workspace: the caller's, or the graph's cached one (grown on demand).
+static bc_status get_ws(bc_graph* g, size_t need, void* user, size_t user_bytes, char** out) {
+  if (user) {
+    if (user_bytes < need) return fail(BC_E_OUT_OF_MEMORY, "workspace smaller than bc_workspace_size()");
+    *out = (char*)user;
+    return BC_OK;
+  }
+  if (g->ws_bytes < need) {
+    if (g->ws) HIPCHK(hipFree(g->ws));
+    g->ws = nullptr;
+    g->ws_bytes = 0;
+    if (hipMalloc(&g->ws, need) != hipSuccess) return fail(BC_E_OUT_OF_MEMORY, "workspace allocation failed");
+    g->ws_bytes = need;
+  }
+  *out = (char*)g->ws;
+  return BC_OK;
+}
+
+// The groups whose vertex is listed (every group of that vertex: several
+// result slots may traverse the same vertex).
+static std::vector<Group> groups_at(int32_t n, const std::vector<Group>& groups, const std::vector<int32_t>& vs) {
+  std::vector<char> mark((size_t)n, 0);
+  for (int32_t v : vs) if (v >= 0 && v < n) mark[v] = 1;
+  std::vector<Group> out;
+  for (const auto& gr : groups) if (mark[gr.v]) out.push_back(gr);
+  return out;
+}
+
+// Runs groups in the chosen mode; in batched mode, batches that exceed a
+// list capacity (they add nothing) are rerun once with worst-case lists.
+static bc_status run_groups(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg,
+                            const std::vector<Group>& groups, const std::vector<Triple>& triples, void* user_ws,
+                            size_t user_bytes, hipStream_t st, double* const* slots, int nslots, CallOut* out) {
+  char* ws = nullptr;
+  bc_status s = get_ws(g, ws_bytes_for(g, r, 32), user_ws, user_bytes, &ws);
+  if (s != BC_OK) return s;
+  if (r.mode == BC_MODE_PLAIN) {
+    s = run_plain(g, r, ext, tg, groups, ws, st, slots[0], nullptr, out);
+    if (s == BC_OK && out->err) return fail(BC_E_CAPACITY, "level-list capacity exceeded");
+    return s;
+  }
+  s = run_batched(g, r, ext, tg, groups, triples, ws, 32, st, slots, nslots, nullptr, out, nullptr);
+  if (s != BC_OK || out->fail.empty()) return s;
+  if (user_ws) return fail(BC_E_CAPACITY, "level-list capacity exceeded; some batches added nothing");
+  // rerun the failed batches' sources without derivation, with lists sized for the worst case
+  std::vector<Group> again = groups_at(g->n, groups, out->fail);
+  s = get_ws(g, ws_bytes_for(g, r, r.B), nullptr, 0, &ws);
+  if (s != BC_OK) return s;
+  CallOut o2;
+  s = run_batched(g, r, ext, tg, again, {}, ws, r.B, st, slots, nslots, nullptr, &o2, nullptr);
+  if (s != BC_OK) return s;
+  if (!o2.fail.empty()) return fail(BC_E_CAPACITY, "level-list capacity exceeded at worst-case size");
+  for (int i = 0; i < kStCount; ++i) out->st[i] += o2.st[i];
+  out->ovf.insert(out->ovf.end(), o2.ovf.begin(), o2.ovf.end());
+  out->fail.clear();
+  return BC_OK;
+}
+
+// The full compute path shared by bc_compute and the server: `slots[i]` is
+// the device score array of result slot i (Group::slot).
+bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& groups, int64_t credited,
+                         void* workspace, size_t ws_bytes, hipStream_t st, double* const* slots, int nslots,
+                         bc_run_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  HIPCHK(hipSetDevice(g->ctx->device));
+  const TravGraph tg = trav(g, r.deg1);
+  std::vector<Triple> triples;
+  if (r.deg2) choose_deg2(g->n, tg.h_rp, tg.h_ci, groups, &triples);
+  bc_run_stats rs{};
+  for (int i = 0; i < 8; ++i) rs.first_overflow[i] = -1;
+  rs.sources = credited;
+  rs.traversed = (int64_t)groups.size() - (int64_t)triples.size();
+  rs.derived = (int64_t)triples.size();
+  rs.te = (double)credited * (double)(g->nnz / 2);
+  const bool ext0 = r.sigma_mode == BC_SIGMA_EXTENDED;
+  CallOut co;
+  bc_status s = run_groups(g, r, ext0, tg, groups, triples, workspace, ws_bytes, st, slots, nslots, &co);
+  if (s != BC_OK) return s;
+  add_stats(&rs, co);
+  std::vector<int32_t> ov = co.ovf;
+  std::sort(ov.begin(), ov.end());
+  ov.erase(std::unique(ov.begin(), ov.end()), ov.end());
+  rs.overflowed = (int64_t)ov.size();
+  for (size_t i = 0; i < ov.size() && i < 8; ++i) rs.first_overflow[i] = ov[i];
+  if (!ov.empty() && r.sigma_mode == BC_SIGMA_AUTO) {
+    std::vector<Group> again = groups_at(g->n, groups, ov);
+    CallOut c2;
+    s = run_groups(g, r, true, tg, again, {}, workspace, ws_bytes, st, slots, nslots, &c2);
+    if (s != BC_OK) return s;
+    add_stats(&rs, c2);
+    rs.rerun_extended = (int64_t)again.size();
+  }
+  rs.raw_te = (double)rs.traversed * (double)(tg.nnz / 2);
+  rs.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = rs;
+  return BC_OK;
+}
+
+bc_status resolve_opts(const bc_graph* g, const bc_compute_opts* o, Resolved* r) { return resolve(g, o, r); }
+
+void graph_groups(const bc_graph* g, const Resolved& r, const int32_t* sources, int64_t k, std::vector<Group>* groups,
+                  int64_t* credited) {
+  map_sources(g->n, g->h_rp.data(), r.deg1 ? &g->pr : nullptr, sources, k, groups, credited);
+}
+
+int64_t graph_n(const bc_graph* g) { return g->n; }
+int context_device(const bc_context* c) { return c->device; }
+int64_t graph_nnz(const bc_graph* g) { return g->nnz; }
+int graph_device(const bc_graph* g) { return g->ctx->device; }
+size_t graph_ws_bytes(const bc_graph* g, const Resolved& r) { return ws_bytes_for(g, r, 32); }
+
+}  // namespace bcx
+
+extern "C" {
+
+bc_status bc_workspace_size(const bc_graph* g, const bc_compute_opts* opts, size_t* bytes) {
+  if (!g || !bytes) return fail(BC_E_INVALID_ARG, "null argument");
+  Resolved r;
+  bc_status s = resolve(g, opts, &r);
+  if (s != BC_OK) return s;
+  *bytes = ws_bytes_for(g, r, 32);
+  return BC_OK;
+}
+
+bc_status bc_compute(bc_graph* g, const int32_t* sources, int64_t k, const bc_compute_opts* opts, void* workspace,
+                     size_t ws_bytes, void* stream, bc_run_stats* stats) {
+  if (!g) return fail(BC_E_INVALID_ARG, "null graph");
+  std::lock_guard<std::mutex> lk(g->mu);
+  Resolved r;
+  bc_status s = resolve(g, opts, &r);
+  if (s != BC_OK) return s;
+  if (k < 0 || (!sources && k != 0 && k != g->n)) return fail(BC_E_INVALID_ARG, "bad source count");
+  if (!sources) k = g->n;
+  for (int64_t i = 0; sources && i < k; ++i)
+    if (sources[i] < 0 || sources[i] >= g->n) return fail(BC_E_INVALID_ARG, "source id out of range");
+  std::vector<Group> groups;
+  int64_t credited = 0;
+  map_sources(g->n, g->h_rp.data(), r.deg1 ? &g->pr : nullptr, sources, k, &groups, &credited);
+  double* slots[1] = {g->d_bc};
+  return compute_groups(g, r, groups, credited, workspace, ws_bytes, (hipStream_t)stream, slots, 1, stats);
+}
+
+bc_status bc_scores(const bc_graph* g, double* out, int32_t norm, int32_t out_on_device) {
+  if (!g || !out) return fail(BC_E_INVALID_ARG, "null argument");
+  if (norm != BC_RAW && norm != BC_UNDIRECTED) return fail(BC_E_INVALID_ARG, "unknown normalisation");
+  HIPCHK(hipSetDevice(g->ctx->device));
+  std::vector<double> h((size_t)g->n);
+  HIPCHK(hipMemcpy(h.data(), g->d_bc, sizeof(double) * g->n, hipMemcpyDeviceToHost));
+  if (norm == BC_UNDIRECTED) for (auto& x : h) x *= 0.5;
+  if (out_on_device) HIPCHK(hipMemcpy(out, h.data(), sizeof(double) * g->n, hipMemcpyHostToDevice));
+  else memcpy(out, h.data(), sizeof(double) * g->n);
+  return BC_OK;
+}
+
+bc_status bc_scores_reset(bc_graph* g) {
+  if (!g) return fail(BC_E_INVALID_ARG, "null graph");
+  HIPCHK(hipSetDevice(g->ctx->device));
+  HIPCHK(hipMemset(g->d_bc, 0, sizeof(double) * g->n));
+  return BC_OK;
+}
+
+bc_status bc_trace(bc_graph* g, const int32_t* sources, int64_t k, const bc_compute_opts* opts, int32_t* d,
+                   uint64_t* sigma, double* sigma_mant, int32_t* sigma_exp, double* delta, int32_t* overflow) {
+  if (!g || !sources || k <= 0) return fail(BC_E_INVALID_ARG, "bad arguments");
+  std::lock_guard<std::mutex> lk(g->mu);
+  Resolved r;
+  bc_status s = resolve(g, opts, &r);
+  if (s != BC_OK) return s;
+  if (r.deg1 || r.deg2) return fail(BC_E_INVALID_ARG, "traces run on the unpruned graph without heuristics");
+  for (int64_t i = 0; i < k; ++i)
+    if (sources[i] < 0 || sources[i] >= g->n) return fail(BC_E_INVALID_ARG, "source id out of range");
+  HIPCHK(hipSetDevice(g->ctx->device));
+  const int64_t n = g->n;
+  const TravGraph tg = trav(g, false);
+  hipStream_t st = nullptr;
+  const bool ext_only = r.sigma_mode == BC_SIGMA_EXTENDED;
+  const bool rerun = r.sigma_mode == BC_SIGMA_AUTO;
+  char* ws = nullptr;
+  s = get_ws(g, ws_bytes_for(g, r, r.B), nullptr, 0, &ws);
+  if (s != BC_OK) return s;
+  std::vector<int32_t> ovf_row((size_t)k, 0);
+
+  if (r.mode == BC_MODE_PLAIN) {
+    PlainWs w;
+    plain_layout(n, g->nnz, ws, &w);
+    for (int64_t i = 0; i < k; ++i) {
+      const std::vector<Group> one{Group{sources[i], 1.0, 0, 0}};
+      for (int pass = 0; pass < 2; ++pass) {
+        const bool ext = ext_only || pass == 1;
+        HIPCHK(hipMemset(w.delta, 0, sizeof(double) * n));
+        HIPCHK(hipMemset(w.bc_tmp, 0, sizeof(double) * n));
+        CallOut co;
+        s = run_plain(g, r, ext, tg, one, ws, st, w.bc_tmp, w.delta, &co);
+        if (s != BC_OK) return s;
+        if (co.err) return fail(BC_E_CAPACITY, "capacity exceeded");
+        if (pass == 0 && !ext) ovf_row[i] = co.ovf.empty() ? 0 : 1;
+        if (d) HIPCHK(hipMemcpy(d + i * n, w.d, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+        if (!ext) {
+          std::vector<uint64_t> sg((size_t)n);
+          HIPCHK(hipMemcpy(sg.data(), w.sig, sizeof(uint64_t) * n, hipMemcpyDeviceToHost));
+          if (sigma) memcpy(sigma + i * n, sg.data(), sizeof(uint64_t) * n);
+          if (sigma_mant) for (int64_t v = 0; v < n; ++v) sigma_mant[i * n + v] = (double)sg[v];
+          if (sigma_exp) memset(sigma_exp + i * n, 0, sizeof(int32_t) * n);
+        } else {
+          if (sigma) memset(sigma + i * n, 0, sizeof(uint64_t) * n);
+          if (sigma_mant) HIPCHK(hipMemcpy(sigma_mant + i * n, w.sm, sizeof(double) * n, hipMemcpyDeviceToHost));
+          if (sigma_exp) HIPCHK(hipMemcpy(sigma_exp + i * n, w.se, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+        }
+        if (delta) HIPCHK(hipMemcpy(delta + i * n, w.delta, sizeof(double) * n, hipMemcpyDeviceToHost));
+        if (ext || !ovf_row[i] || !rerun) break;
+      }
+    }
+    if (overflow) memcpy(overflow, ovf_row.data(), sizeof(int32_t) * k);
+    return BC_OK;
+  }
+
+  // batched traces: every source its own lane, all in result slot 0 (scratch)
+  const int B = r.B;
+  BatchWs w;
+  batch_layout(n, g->nnz, B, B, ws, &w);
+  const size_t cells = (size_t)B * n;
+  double *dd = nullptr, *dbc = nullptr;
+  uint64_t* dsg = nullptr;
+  int32_t* dse = nullptr;
+  bc_status res = BC_OK;
+  if (hipMalloc((void**)&dd, sizeof(double) * cells) != hipSuccess ||
+      hipMalloc((void**)&dsg, sizeof(uint64_t) * cells) != hipSuccess ||
+      hipMalloc((void**)&dse, sizeof(int32_t) * cells) != hipSuccess ||
+      hipMalloc((void**)&dbc, sizeof(double) * n) != hipSuccess)
+    res = fail(BC_E_OUT_OF_MEMORY, "trace buffers");
+  std::vector<int32_t> lv((size_t)n * B);
+  std::vector<uint64_t> vis((size_t)n * r.K);
+  std::vector<double> hd(cells), hm;
+  std::vector<uint64_t> hs;
+  std::vector<int32_t> he;
+  double* slots[1] = {dbc};
+  for (int64_t b0 = 0; b0 < k && res == BC_OK; b0 += B) {
+    const int64_t nb = std::min<int64_t>(B, k - b0);
+    for (int pass = 0; pass < 2 && res == BC_OK; ++pass) {
+      const bool ext = ext_only || pass == 1;
+      std::vector<Group> run;
+      std::vector<int64_t> row;  // trace row of each group
+      for (int64_t i = 0; i < nb; ++i) {
+        if (pass == 1 && !ovf_row[b0 + i]) continue;
+        run.push_back(Group{sources[b0 + i], 1.0, 0, 0});
+        row.push_back(b0 + i);
+      }
+      if (run.empty()) break;
+      if (hipMemset(dd, 0, sizeof(double) * cells) != hipSuccess) { res = fail(BC_E_DEVICE, "memset"); break; }
+      TraceDev tdv{dd, dsg, (double*)dsg, dse, dbc};
+      CallOut co;
+      std::vector<int32_t> lanes;
+      res = run_batched(g, r, ext, tg, run, {}, ws, B, st, slots, 1, &tdv, &co, &lanes);
+      if (res != BC_OK) break;
+      if (!co.fail.empty()) { res = fail(BC_E_CAPACITY, "capacity exceeded"); break; }
+      if (hipMemcpy(lv.data(), w.lv, sizeof(int32_t) * lv.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(vis.data(), w.vis, sizeof(uint64_t) * vis.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(hd.data(), dd, sizeof(double) * cells, hipMemcpyDeviceToHost) != hipSuccess) {
+        res = fail(BC_E_DEVICE, "trace copy");
+        break;
+      }
+      if (ext) {
+        hm.resize(cells);
+        he.resize(cells);
+        (void)hipMemcpy(hm.data(), dsg, sizeof(double) * cells, hipMemcpyDeviceToHost);
+        (void)hipMemcpy(he.data(), dse, sizeof(int32_t) * cells, hipMemcpyDeviceToHost);
+      } else {
+        hs.resize(cells);
+        (void)hipMemcpy(hs.data(), dsg, sizeof(uint64_t) * cells, hipMemcpyDeviceToHost);
+      }
+      std::vector<char> wrapped(run.size(), 0);
+      for (int32_t v : co.ovf)
+        for (size_t gi = 0; gi < run.size(); ++gi)
+          if (run[gi].v == v) wrapped[gi] = 1;
+      for (int j = 0; j < B; ++j) {
+        const int32_t gi = lanes[j];
+        if (gi < 0) continue;
+        const int64_t rw = row[gi];
+        if (pass == 0 && !ext) ovf_row[rw] = wrapped[gi];
+        for (int64_t v = 0; v < n; ++v) {
+          const bool reached = (vis[(size_t)v * r.K + (j >> 6)] >> (j & 63)) & 1ull;
+          const size_t c = (size_t)j * n + v;
+          if (d) d[rw * n + v] = reached ? lv[(size_t)v * B + j] : -1;
+          if (ext) {
+            if (sigma) sigma[rw * n + v] = 0;
+            if (sigma_mant) sigma_mant[rw * n + v] = hm[c];
+            if (sigma_exp) sigma_exp[rw * n + v] = he[c];
+          } else {
+            if (sigma) sigma[rw * n + v] = hs[c];
+            if (sigma_mant) sigma_mant[rw * n + v] = (double)hs[c];
+            if (sigma_exp) sigma_exp[rw * n + v] = 0;
+          }
+          if (delta) delta[rw * n + v] = hd[c];
+        }
+      }
+      if (ext || !rerun) break;
+    }
+  }
+  if (dd) (void)hipFree(dd);
+  if (dsg) (void)hipFree(dsg);
+  if (dse) (void)hipFree(dse);
+  if (dbc) (void)hipFree(dbc);
+  if (res == BC_OK && overflow) memcpy(overflow, ovf_row.data(), sizeof(int32_t) * k);
+  return res;
+}
+
+}  // extern "C"

@@ -1,0 +1,34 @@
+// Internal entry points shared by the C ABI and the serving loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/bc.h"
+#include "bc_host.h"
+
+namespace bcx {
+
+bc_status fail(bc_status st, const std::string& msg);
+
+// Options after defaults and checks.
+struct Resolved {
+  int mode, B, K, block, grid_per_cu, sigma_mode;
+  bool deg1, deg2;
+  double alpha;
+};
+bc_status resolve_opts(const bc_graph* g, const bc_compute_opts* o, Resolved* r);
+void graph_groups(const bc_graph* g, const Resolved& r, const int32_t* sources, int64_t k, std::vector<Group>* groups,
+                  int64_t* credited);
+bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& groups, int64_t credited,
+                         void* workspace, size_t ws_bytes, hipStream_t st, double* const* slots, int nslots,
+                         bc_run_stats* stats);
+int64_t graph_n(const bc_graph* g);
+int context_device(const bc_context* c);
+int64_t graph_nnz(const bc_graph* g);
+int graph_device(const bc_graph* g);
+size_t graph_ws_bytes(const bc_graph* g, const Resolved& r);
+
+}  // namespace bcx

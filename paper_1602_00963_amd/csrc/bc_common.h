@@ -1,0 +1,205 @@
+// Internal declarations shared by the HIP kernels and the host runtime.
+// Wave64 primitives for gfx950 and the device-side bookkeeping structures
+// of the forward (shortest-path counting) and backward (dependency) sweeps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bc.h"
+
+namespace bcx {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------ wave helpers
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
+
+// Number of set bits of `mask` strictly below the calling lane.
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+template <typename T>
+__device__ __forceinline__ T shfl(T v, int src) { return __shfl(v, src, kWave); }
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Butterfly sum in a fixed order: every lane ends with the same total.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Inclusive prefix sum of a 64-bit value over the wave (Hillis-Steele).
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    uint64_t t = __shfl_up(v, o, kWave);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+// ----------------------------------------------------- extended-range counts
+// A path count too large for uint64 is held as (m, e) = m * 2^e with m in
+// [1, 2) (or 0).  Sums align to the larger exponent; terms smaller by more
+// than 2^-1074 relative vanish, far below the 1e-9 tolerance.
+
+struct Ext {
+  double m;
+  int32_t e;
+};
+
+__device__ __forceinline__ Ext ext_zero() { return Ext{0.0, INT32_MIN / 2}; }
+
+__device__ __forceinline__ Ext ext_add(Ext a, Ext b) {
+  if (a.m == 0.0) return b;
+  if (b.m == 0.0) return a;
+  if (a.e >= b.e) {
+    int d = b.e - a.e;
+    return Ext{a.m + (d < -1100 ? 0.0 : ldexp(b.m, d)), a.e};
+  }
+  int d = a.e - b.e;
+  return Ext{b.m + (d < -1100 ? 0.0 : ldexp(a.m, d)), b.e};
+}
+
+__device__ __forceinline__ Ext ext_norm(Ext a) {
+  if (a.m == 0.0) return ext_zero();
+  int k;
+  double f = frexp(a.m, &k);  // f in [0.5, 1)
+  return Ext{f * 2.0, a.e + k - 1};
+}
+
+// ------------------------------------------------------------ work records
+
+// One unit of edge work: chunk `c` (edges [c*CH, (c+1)*CH) of the entry's
+// adjacency) of level-list entry `e`.  Entries whose adjacency spans several
+// chunks ("split" entries) also carry `mi`, a run-unique index of their
+// arrival counter, and `pb`, the level-relative base of their partial-sum
+// slots; single-chunk entries have mi = -1.
+struct Unit {
+  int32_t e;
+  int32_t c;
+  int32_t mi;
+  int32_t pb;
+};
+
+// Per-level counters of a level list, written by atomic appends during the
+// discovering phase of the previous level.  `packed` = entries << 32 | units.
+struct LevelCtr {
+  unsigned long long packed;
+  int32_t multi;      // split entries appended (run-unique indices taken from a global counter)
+  int32_t pslots;     // partial-sum slots reserved (level-relative)
+  unsigned long long fedges;  // sum of degrees of the appended entries
+  int32_t err;        // capacity errors raised while this level's list was built
+  int32_t pad;
+};
+// Every workgroup reads a level's counters only after the barrier that ends
+// the phase building that level, so all of them take the same decisions.
+
+// Errors raised inside a persistent kernel; the host maps them to bc_status.
+enum DevErr : int32_t { kErrNone = 0, kErrCapEntries = 1, kErrCapUnits = 2, kErrCapPartials = 4, kErrCapMulti = 8 };
+
+}  // namespace bcx
+
+namespace bcx {
+
+// Level lists: the stacked queue Q of the paper's Alg. 2 (Q with offsets
+// Q_off), extended with a work-unit list so that long adjacency lists are
+// split across waves.  Entries of level l occupy Q[ebase(l) .. ebase(l+1)),
+// their units U[ubase(l) .. ubase(l+1)).
+struct Lists {
+  int32_t* Q;
+  Unit* U;
+  LevelCtr* lc;
+  int32_t* arrive;   // arrival counters of split entries (run-unique index)
+  int32_t* gmulti;   // next split-entry index
+  int32_t* err;
+  const int32_t* rp;
+  int32_t cap_entries, cap_units, cap_parts, cap_multi;
+};
+
+__device__ __forceinline__ void raise_err(const Lists& L, int lvl, int32_t code) {
+  atomicOr(&L.lc[lvl].err, code);
+  atomicOr(L.err, code);
+}
+
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// Wave-aggregated append of the lanes with `want` to level `lvl`'s list:
+// one 64-bit atomic per wave reserves both the entry positions and the
+// unit positions (entries << 32 | units), lanes take their slots by an
+// inclusive scan.  Adds the appended degrees to the level's frontier-edge
+// counter.  Returns the number of lanes appended (uniform).
+template <int CH>
+__device__ __forceinline__ int append_entries(const Lists& L, int lvl, int32_t ebase, int32_t ubase,
+                                              bool want, int32_t vtx) {
+  const uint64_t wmask = ballot(want);
+  if (wmask == 0) return 0;
+  int32_t deg = 0, nunits = 0;
+  if (want) {
+    deg = L.rp[vtx + 1] - L.rp[vtx];
+    nunits = deg <= CH ? 1 : (deg + CH - 1) / CH;
+  }
+  const uint64_t contrib = want ? ((1ull << 32) | (uint64_t)(uint32_t)nunits) : 0ull;
+  const uint64_t incl = wave_incl_scan_u64(contrib);
+  const uint64_t total = shfl(incl, kWave - 1);
+  const uint64_t dsum = wave_sum_u64(want ? (uint64_t)deg : 0ull);
+  unsigned long long base = 0;
+  if (lane_id() == kWave - 1) {
+    base = atomicAdd(&L.lc[lvl].packed, (unsigned long long)total);
+    atomicAdd(&L.lc[lvl].fedges, (unsigned long long)dsum);
+  }
+  base = shfl((uint64_t)base, kWave - 1);
+  if (want) {
+    const uint64_t my = base + incl - contrib;
+    const int64_t e = (int64_t)ebase + (int64_t)(my >> 32);
+    const int64_t u = (int64_t)ubase + (int64_t)(my & 0xffffffffull);
+    if (e >= L.cap_entries) {
+      raise_err(L, lvl, kErrCapEntries);
+    } else if (u + nunits > L.cap_units) {
+      raise_err(L, lvl, kErrCapUnits);
+    } else {
+      L.Q[e] = vtx;
+      if (nunits == 1) {
+        L.U[u] = Unit{(int32_t)e, 0, -1, 0};
+      } else {
+        const int32_t mi = atomicAdd(L.gmulti, 1);
+        const int32_t pb = atomicAdd(&L.lc[lvl].pslots, nunits);
+        atomicAdd(&L.lc[lvl].multi, 1);
+        if (mi >= L.cap_multi) {
+          raise_err(L, lvl, kErrCapMulti);
+        } else if (pb + nunits > L.cap_parts) {
+          raise_err(L, lvl, kErrCapPartials);
+        } else {
+          L.arrive[mi] = 0;
+          for (int32_t c = 0; c < nunits; ++c) L.U[u + c] = Unit{(int32_t)e, c, mi, pb};
+        }
+      }
+    }
+  }
+  return __popcll(wmask);
+}
+
+// Units of a split entry with degree deg.
+template <int CH>
+__device__ __forceinline__ int32_t units_of(int32_t deg) { return deg <= CH ? 1 : (deg + CH - 1) / CH; }
+
+}  // namespace bcx

@@ -1,0 +1,162 @@
+// Host-side graph preparation: CSR validation, the 1-degree reduction
+// (Sec. 3.5.1, Alg. 6), mapping requested sources onto traversal sources
+// with weights (Eq. (4)-(5)), and the choice of 2-degree vertices whose
+// forward sweep is derived from their neighbours' (Sec. 3.5.2).
+#include "bc_host.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+
+namespace bcx {
+
+bool validate_csr(int32_t n, const int32_t* rp, const int32_t* ci, int64_t nnz, std::string* why) {
+  char buf[256];
+  if (n < 0) { *why = "n < 0"; return false; }
+  if (nnz < 0 || nnz > INT32_MAX) { *why = "nnz out of range (must fit int32)"; return false; }
+  if (rp[0] != 0) { *why = "row_ptr[0] != 0"; return false; }
+  if ((int64_t)rp[n] != nnz) {
+    snprintf(buf, sizeof buf, "row_ptr[n] = %d but nnz = %lld", rp[n], (long long)nnz);
+    *why = buf;
+    return false;
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    if (rp[v + 1] < rp[v]) {
+      snprintf(buf, sizeof buf, "row_ptr decreases at vertex %d", v);
+      *why = buf;
+      return false;
+    }
+  }
+  for (int32_t v = 0; v < n; ++v) {
+    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+      const int32_t w = ci[e];
+      if (w < 0 || w >= n) {
+        snprintf(buf, sizeof buf, "vertex %d has neighbour id %d outside [0, n)", v, w);
+        *why = buf;
+        return false;
+      }
+      if (w == v) {
+        snprintf(buf, sizeof buf, "self-loop at vertex %d", v);
+        *why = buf;
+        return false;
+      }
+    }
+  }
+  // duplicates: sort a copy of each row; symmetry: every (v, w) has (w, v)
+  std::vector<int32_t> row;
+  std::vector<int64_t> fill(rp, rp + n);  // cursor per vertex for the transpose
+  std::vector<int32_t> tr((size_t)nnz);
+  for (int32_t v = 0; v < n; ++v) {
+    row.assign(ci + rp[v], ci + rp[v + 1]);
+    std::sort(row.begin(), row.end());
+    for (size_t i = 1; i < row.size(); ++i) {
+      if (row[i] == row[i - 1]) {
+        snprintf(buf, sizeof buf, "duplicate edge (%d, %d)", v, row[i]);
+        *why = buf;
+        return false;
+      }
+    }
+    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+      const int32_t w = ci[e];
+      if (fill[w] >= rp[w + 1]) {
+        snprintf(buf, sizeof buf, "asymmetric: vertex %d has more in-edges than out-edges", w);
+        *why = buf;
+        return false;
+      }
+      tr[(size_t)fill[w]++] = v;
+    }
+  }
+  // the transpose rows must equal the rows as sets
+  for (int32_t v = 0; v < n; ++v) {
+    row.assign(ci + rp[v], ci + rp[v + 1]);
+    std::vector<int32_t> t(tr.begin() + rp[v], tr.begin() + rp[v + 1]);
+    std::sort(row.begin(), row.end());
+    std::sort(t.begin(), t.end());
+    if (row != t) {
+      snprintf(buf, sizeof buf, "asymmetric adjacency at vertex %d", v);
+      *why = buf;
+      return false;
+    }
+  }
+  return true;
+}
+
+void prune_deg1(int32_t n, const int32_t* rp, const int32_t* ci, Pruned* out) {
+  out->omega.assign((size_t)n, 0);
+  out->kind.assign((size_t)n, 0);
+  out->hub.assign((size_t)n, -1);
+  auto deg = [&](int32_t v) { return rp[v + 1] - rp[v]; };
+  for (int32_t u = 0; u < n; ++u) {
+    const int32_t du = deg(u);
+    if (du == 0) { out->kind[u] = kIsolated; continue; }
+    if (du != 1) continue;
+    const int32_t v = ci[rp[u]];
+    if (deg(v) >= 2) {
+      out->kind[u] = kPendant;
+      out->hub[u] = v;
+      out->omega[v] += 1;
+    } else {
+      out->kind[u] = kK2;
+    }
+  }
+  out->rp.assign((size_t)n + 1, 0);
+  out->ci.clear();
+  out->ci.reserve((size_t)rp[n]);
+  for (int32_t v = 0; v < n; ++v) {
+    if (out->kind[v] == kKept) {
+      for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+        const int32_t w = ci[e];
+        if (out->kind[w] == kKept) out->ci.push_back(w);
+      }
+    }
+    out->rp[v + 1] = (int32_t)out->ci.size();
+  }
+}
+
+void map_sources(int32_t n, const int32_t* rp, const Pruned* pr, const int32_t* src, int64_t k,
+                 std::vector<Group>* groups, int64_t* credited) {
+  std::vector<double> w((size_t)n, 0.0);
+  std::vector<int32_t> own((size_t)n, 0);
+  std::vector<char> seen((size_t)n, 0);
+  std::vector<int32_t> order;
+  int64_t cred = 0;
+  auto add = [&](int32_t v, double wt, int32_t ow) {
+    if (!seen[v]) { seen[v] = 1; order.push_back(v); }
+    w[v] += wt;
+    own[v] += ow;
+  };
+  for (int64_t i = 0; i < k; ++i) {
+    const int32_t s = src ? src[i] : (int32_t)i;
+    if (rp[s + 1] == rp[s]) continue;  // isolated: no pairs
+    ++cred;
+    if (!pr) { add(s, 1.0, 0); continue; }
+    switch (pr->kind[s]) {
+      case kKept: add(s, 1.0, 0); break;
+      case kPendant: add(pr->hub[s], 1.0, 1); break;
+      default: break;  // ends of 2-vertex components: no inner vertices
+    }
+  }
+  groups->clear();
+  groups->reserve(order.size());
+  for (int32_t v : order) groups->push_back(Group{v, w[v], own[v], 0});
+  *credited = cred;
+}
+
+void choose_deg2(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<Group>& groups,
+                 std::vector<Triple>* triples) {
+  triples->clear();
+  std::vector<int32_t> gi((size_t)n, -1);
+  for (size_t i = 0; i < groups.size(); ++i) gi[groups[i].v] = (int32_t)i;
+  std::vector<char> used(groups.size(), 0);
+  for (size_t i = 0; i < groups.size(); ++i) {
+    const int32_t c = groups[i].v;
+    if (used[i] || rp[c + 1] - rp[c] != 2) continue;
+    const int32_t a = ci[rp[c]], b = ci[rp[c] + 1];
+    const int32_t ia = gi[a], ib = gi[b];
+    if (ia < 0 || ib < 0 || used[ia] || used[ib]) continue;
+    used[i] = used[ia] = used[ib] = 1;
+    triples->push_back(Triple{ia, ib, (int32_t)i});
+  }
+}
+
+}  // namespace bcx

@@ -1,0 +1,123 @@
+// Kernel argument blocks and launchers (host-visible).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bc_common.h"
+
+namespace bcx {
+
+// Global run counters accumulated by the kernels (device, uint64 each).
+enum StatIdx : int {
+  kStLevels = 0,
+  kStBuLevels = 1,
+  kStReached = 2,
+  kStReachedNnz = 3,
+  kStDag = 4,
+  kStLaunches = 5,
+  kStCount = 8
+};
+
+struct PlainArgs {
+  int32_t n;
+  int64_t nnz;
+  const int32_t* rp;
+  const int32_t* ci;
+  const int32_t* omega;       // pendants per vertex, or null
+  const int2* gu;             // static units (vertex, chunk) of every vertex with edges
+  int32_t ngu;
+  int32_t* d;
+  uint64_t* sig;              // exact counts
+  double* sm;                 // extended counts: significand
+  int32_t* se;                //                  exponent
+  double* psi;                // (1 + delta + omega) / sigma  (extended: over the significand)
+  int32_t* Q;
+  Unit* U;
+  int32_t* qoff;
+  int32_t* uoff;
+  LevelCtr* lc;
+  double* part_m;
+  int32_t* part_e;
+  int32_t* arrive;
+  int32_t* gmulti;
+  int32_t* err;
+  int32_t* ovf_now;           // set when a count wraps in this launch
+  int32_t* ovf_list;          // sources that wrapped (host reruns them extended)
+  int32_t* ovf_count;
+  uint64_t* ns;               // component size accumulator (1-degree own term)
+  unsigned long long* stats;  // StatIdx counters
+  double* bc;
+  double* delta_out;          // per-vertex delta of this source (trace), or null
+  int32_t src;
+  int32_t own;                // pendant sources of src represented by this launch
+  double weight;              // sources represented by src's sweep
+  double alpha;
+  int32_t cap_entries, cap_units, cap_parts, cap_multi, cap_levels;
+};
+
+struct BatchArgs {
+  int32_t n;
+  int64_t nnz;
+  int32_t K;                  // 64-lane words per vertex (batch = 64 K)
+  const int32_t* rp;
+  const int32_t* ci;
+  const int32_t* omega;
+  const int2* gu;             // static units (vertex, chunk) for bottom-up levels
+  int32_t ngu;
+  int32_t* lv;                // [n][64K] level per (vertex, lane), valid where vis bit set
+  uint64_t* sig;              // [n][64K] exact counts; psi overwrites them in the backward sweep
+  double* sm;                 // [n][64K] extended significand (psi overwrites)
+  int32_t* se;                // [n][64K] extended exponent
+  uint64_t* vis;              // [n][K] lanes that reached the vertex
+  uint64_t* fm;               // [3][n][K] rotating per-level lane masks
+  int32_t* stamp;             // [n] last level the vertex was appended to
+  int32_t* Q;
+  Unit* U;
+  int32_t* qoff;
+  int32_t* uoff;
+  LevelCtr* lc;
+  double* part_m;             // [slot][K][64]
+  int32_t* part_e;
+  int32_t* arrive;
+  int32_t* gmulti;
+  int32_t* err;
+  uint32_t* lane_ovf;         // [64K] lanes whose count wrapped
+  int32_t* ovf_list;          // sources of wrapped lanes, appended per batch (host reruns them)
+  int32_t* ovf_count;
+  int32_t* fail_list;         // sources of batches that hit a list capacity (host reruns them)
+  int32_t* fail_count;
+  unsigned long long* lane_ns;// [64K] component sizes (1-degree own term)
+  unsigned long long* stats;
+  double* delta_out;          // trace: [64K][n] dependencies, or null
+  uint64_t* sig_out;          // trace: [64K][n] counts copied before the backward sweep, or null
+  double* sm_out;             // trace (extended)
+  int32_t* se_out;
+  // batch description (device arrays, 64K entries each)
+  const int32_t* lane_src;    // source vertex of each lane, -1 = inactive
+  const double* lane_w;       // sources represented by the lane's sweep
+  const int32_t* lane_own;    // pendant sources represented (own term)
+  const int8_t* lane_pa;      // derived lanes: partner lanes (same word), -1 if traversed
+  const int8_t* lane_pb;
+  const int8_t* lane_slot;    // result array of each lane (index into slot_bc)
+  double* const* slot_bc;     // per-slot score arrays (device), up to 64
+  const uint64_t* edge_lanes; // [K] lanes that propagate along edges (active, not derived)
+  const int32_t* l0;          // distinct source vertices of the batch
+  int32_t nl0;
+  int32_t has_derived;        // any lane derived from two partner lanes
+  int32_t has_own;            // any lane with pendant sources (component sizes needed)
+  unsigned long long* fulledges; // degrees of vertices every edge lane has reached
+  double alpha;
+  int32_t cap_entries, cap_units, cap_parts, cap_multi, cap_levels;
+};
+
+constexpr int kBatchChunk = 256;
+constexpr int kPlainChunkHost = 64;
+
+hipError_t launch_plain(const PlainArgs& a, bool ext, int grid, int block, hipStream_t st);
+hipError_t plain_max_grid(bool ext, int block, int* blocks_per_cu);
+
+hipError_t launch_batch(const BatchArgs& a, bool ext, int grid, int block, hipStream_t st);
+hipError_t batch_max_grid(bool ext, int K, int block, int* blocks_per_cu);
+
+}  // namespace bcx

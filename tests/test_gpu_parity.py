@@ -1,0 +1,262 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Bar: distances and uint64 path counts bit-exact; the set of sources whose
+uint64 count wraps identical to the oracle's; dependencies and scores within
+relative 1e-9 (|a-b| <= 1e-9 max(|a|,|b|), exact where either is 0).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-9
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bcm():
+    import paper_1602_00963_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(bcm):
+    c = bcm.Context(0)
+    yield c
+    c.close()
+
+
+def assert_close(got, ref, rel=REL, what=""):
+    ok = oracle.close(got, ref, rel)
+    if not ok.all():
+        bad = np.nonzero(~ok)[0][:8]
+        raise AssertionError(f"{what}: {int((~ok).sum())} mismatches, e.g. at {bad}: {np.asarray(got)[bad]} vs "
+                             f"{np.asarray(ref)[bad]}")
+
+
+def run_bc(bcm, ctx, g, sources=None, prune=False, **opts):
+    G = bcm.Graph(ctx, g, prune=prune)
+    st = G.compute(sources, **opts)
+    out = G.scores()
+    G.close()
+    return out, st
+
+
+MODES = [dict(mode="plain"), dict(mode="batched", batch=64), dict(mode="batched", batch=128),
+         dict(mode="batched", batch=256)]
+MODE_IDS = ["plain", "b64", "b128", "b256"]
+
+
+@pytest.mark.parametrize("opts", MODES, ids=MODE_IDS)
+def test_rmat_scale10_all_sources(bcm, ctx, opts):
+    """The small R-MAT workload (scale 10, EF 16): every source."""
+    g = gg.config_c1()
+    say("case rmat10 all sources", opts)
+    ref, _ = oracle.bc(g, nthreads=4)
+    got, st = run_bc(bcm, ctx, g, **opts)
+    assert_close(got, ref, what=str(opts))
+    assert st["sources"] == int((g.degrees() > 0).sum())
+
+
+@pytest.mark.parametrize("opts", MODES, ids=MODE_IDS)
+def test_traces_bit_exact(bcm, ctx, opts):
+    """d and sigma bit-exact, delta within tolerance, for sampled sources of a
+    graph spanning several work units per vertex (hubs beyond 256 edges)."""
+    g = gg.rmat(12, 16, 21)
+    assert g.degrees().max() > 3 * 256
+    S = gg.sample(g.non_isolated(), 80, 3)
+    say("case traces rmat12", opts)
+    tr = bcm.Graph(ctx, g).trace(S, **opts)
+    for i, s in enumerate(S):
+        o = oracle.source(g, s)
+        assert not o["overflow"] and not tr["overflow"][i]
+        assert np.array_equal(tr["d"][i], o["d"]), f"d differs for source {s}"
+        assert np.array_equal(tr["sigma"][i], o["sigma"]), f"sigma differs for source {s}"
+        dl = o["delta"].copy()
+        dl[s] = 0.0
+        assert_close(tr["delta"][i], dl, what=f"delta source {s}")
+
+
+@pytest.mark.parametrize("opts", MODES, ids=MODE_IDS)
+def test_closed_forms(bcm, ctx, opts):
+    for g, expect in [
+        (gg.star(40), lambda n: np.r_[(n - 1) * (n - 2) / 2, np.zeros(n - 1)]),
+        (gg.path(70), lambda n: np.array([i * (n - 1 - i) for i in range(n)], dtype=float)),
+        (gg.cycle(65), lambda n: np.full(n, (n - 1) * (n - 3) / 8)),
+        (gg.cycle(64), lambda n: np.full(n, (n - 2) ** 2 / 8)),
+        (gg.complete(30), lambda n: np.zeros(n)),
+        (gg.hypercube(9), lambda n: np.full(n, (9 * 2 ** 8 - 2 ** 9 + 1) / 2)),
+    ]:
+        say("case closed form", g.name, opts)
+        got, _ = run_bc(bcm, ctx, g, **opts)
+        assert_close(got / 2, expect(g.n), what=f"{g.name} {opts}")
+
+
+@pytest.mark.parametrize("opts", MODES[:2], ids=MODE_IDS[:2])
+def test_overflow_sources_and_extended_counts(bcm, ctx, opts):
+    """A 40 x 40 lattice: sources near a corner wrap uint64 (C(78,39) >
+    2^64), central ones do not.  The wrapped set must equal the oracle's,
+    d stays exact, extended counts match the long-double oracle, and scores
+    (computed with the extended rerun) match."""
+    g = gg.full_grid(40, 40)
+    S = np.array([0, 39, 1599, 20 * 40 + 20, 5 * 40 + 7, 19 * 40 + 21, 1560], dtype=np.int32)
+    say("case overflow lattice", opts)
+    tr = bcm.Graph(ctx, g).trace(S, **opts)
+    for i, s in enumerate(S):
+        o = oracle.source(g, s)
+        assert bool(tr["overflow"][i]) == o["overflow"], f"overflow flag differs for {s}"
+        assert np.array_equal(tr["d"][i], o["d"])
+        if o["overflow"]:
+            ext = np.ldexp(tr["sigma_mant"][i], tr["sigma_exp"][i])
+            ref = o["sigma_ld"].astype(np.float64)
+            assert_close(ext, ref, 1e-12, what=f"extended sigma {s}")
+        else:
+            assert np.array_equal(tr["sigma"][i], o["sigma"])
+        dl = o["delta"].copy()
+        dl[s] = 0.0
+        assert_close(tr["delta"][i], dl, what=f"delta {s}")
+    ref, ovf = oracle.bc(g, S)
+    assert ovf.sum() >= 3
+    got, st = run_bc(bcm, ctx, g, S, **opts)
+    assert st["overflowed"] == int(ovf.sum())
+    assert st["rerun_extended"] == int(ovf.sum())
+    assert_close(got, ref, what="lattice scores")
+
+
+def test_layered_chain_overflow_exact_boundary(bcm, ctx):
+    """16 complete bipartite layers of width 16 stay exact; 17 wrap."""
+    for layers, wraps in [(16, False), (17, True)]:
+        g = gg.layered_chain(16, layers)
+        say("case chain", layers)
+        for opts in MODES[:2]:
+            tr = bcm.Graph(ctx, g).trace(np.array([0], np.int32), **opts)
+            assert bool(tr["overflow"][0]) == wraps
+            if not wraps:
+                assert int(tr["sigma"][0][1 + 15 * 16]) == 16 ** 15
+
+
+@pytest.mark.parametrize("opts", MODES[:2] + [MODES[3]], ids=["plain", "b64", "b256"])
+def test_extended_mode_everywhere(bcm, ctx, opts):
+    """Forcing the extended form on a graph without wrap: counts below 2^53
+    are exact in it, scores match."""
+    g = gg.rmat(10, 8, 4)
+    say("case extended everywhere", opts)
+    ref, _ = oracle.bc(g)
+    got, _ = run_bc(bcm, ctx, g, sigma="extended", **opts)
+    assert_close(got, ref, what="extended scores")
+    S = gg.sample(g.non_isolated(), 20, 9)
+    tr = bcm.Graph(ctx, g).trace(S, sigma="extended", **opts)
+    for i, s in enumerate(S):
+        o = oracle.source(g, s)
+        assert np.array_equal(tr["d"][i], o["d"])
+        assert np.array_equal(np.ldexp(tr["sigma_mant"][i], tr["sigma_exp"][i]), o["sigma"].astype(np.float64))
+
+
+@pytest.mark.parametrize("opts", [dict(mode="plain"), dict(mode="batched", batch=64),
+                                  dict(mode="batched", batch=256)], ids=["plain", "b64", "b256"])
+def test_degree1_pruning_equals_unpruned(bcm, ctx, opts):
+    """The 1-degree reduction gives the unpruned scores: all sources and a
+    subset containing pendants, hubs, and ends of 2-vertex components."""
+    g = gg.disjoint_union(gg.rmat_with_pendants(11, 8, 3, 0.3, 33), gg.star(9), gg.path(2), gg.path(3),
+                          gg.cycle(5))
+    say("case deg1", opts)
+    ref, _ = oracle.bc(g)
+    got, st = run_bc(bcm, ctx, g, prune=True, deg1=True, **opts)
+    assert_close(got, ref, what="pruned all")
+    assert st["traversed"] < st["sources"]
+    S = gg.sample(np.arange(g.n, dtype=np.int32), 500, 4)
+    ref_s, _ = oracle.bc(g, S)
+    got_s, _ = run_bc(bcm, ctx, g, S, prune=True, deg1=True, **opts)
+    assert_close(got_s, ref_s, what="pruned subset")
+
+
+@pytest.mark.parametrize("batch", [64, 256])
+def test_degree2_derivation_equals_unpruned(bcm, ctx, batch):
+    """2-degree vertices whose neighbours are sources of the same batch get
+    their sweep derived (Lemma 1, Eq. (6)); scores unchanged."""
+    g = gg.disjoint_union(gg.road_grid(24, 20, 0.2, 0.01, 7), gg.cycle(9), gg.path(7))
+    say("case deg2", batch)
+    ref, _ = oracle.bc(g)
+    got, st = run_bc(bcm, ctx, g, mode="batched", batch=batch, deg2=True)
+    assert st["derived"] > 10
+    assert_close(got, ref, what="deg2")
+    gp = gg.rmat_with_pendants(10, 4, 5, 0.3, 8)
+    ref, _ = oracle.bc(gp)
+    got, st = run_bc(bcm, ctx, gp, prune=True, mode="batched", batch=batch, deg1=True, deg2=True)
+    assert st["derived"] > 0
+    assert_close(got, ref, what="deg1+deg2")
+
+
+def test_sources_with_repeats_and_isolated(bcm, ctx):
+    g = gg.disjoint_union(gg.rmat(9, 8, 2), gg.complete(1))
+    S = np.array([3, 3, 5, g.n - 1, 7, 3], dtype=np.int32)
+    ref, _ = oracle.bc(g, S)
+    for opts in MODES[:2]:
+        got, st = run_bc(bcm, ctx, g, S, **opts)
+        assert_close(got, ref, what=str(opts))
+        assert st["sources"] == 5
+
+
+def test_batched_deterministic(bcm, ctx):
+    g = gg.rmat(12, 16, 5)
+    G = bcm.Graph(ctx, g)
+    G.compute(None, mode="batched", batch=256)
+    a = G.scores()
+    G.reset()
+    G.compute(None, mode="batched", batch=256)
+    b = G.scores()
+    assert np.array_equal(a, b)
+    G.close()
+
+
+def test_run_stats_match_oracle_counts(bcm, ctx):
+    """reached vertices, reached CSR entries and DAG edges summed over the
+    sources equal the oracle's per-source counts."""
+    g = gg.rmat(10, 16, 6)
+    S = gg.sample(g.non_isolated(), 300, 2)
+    _, _, st = oracle.bc(g, S, want_stats=True)
+    for opts in MODES[:2] + [MODES[3]]:
+        _, rs = run_bc(bcm, ctx, g, S, **opts)
+        assert rs["reached"] == st[:, 0].sum()
+        assert rs["reached_nnz"] == st[:, 1].sum()
+        assert rs["dag_edges"] == st[:, 2].sum()
+
+
+def test_rmat_scale16_sampled_sources(bcm, ctx):
+    """The scale-16 workload at full size: 256 sampled sources through the
+    batched launch shape used by the benchmark, and 32 through plain."""
+    g = gg.config_c2()
+    S = gg.sample(g.non_isolated(), 256, 11)
+    say("case rmat16 sampled")
+    ref, _ = oracle.bc(g, S, nthreads=8)
+    got, _ = run_bc(bcm, ctx, g, S, mode="batched", batch=256)
+    assert_close(got, ref, what="rmat16 batched")
+    ref2, _ = oracle.bc(g, S[:32], nthreads=8)
+    got2, _ = run_bc(bcm, ctx, g, S[:32], mode="plain")
+    assert_close(got2, ref2, what="rmat16 plain")
+
+
+def test_device_score_output_and_workspace(bcm, ctx):
+    import torch
+    g = gg.rmat(9, 8, 3)
+    ref, _ = oracle.bc(g)
+    G = bcm.Graph(ctx, g)
+    nbytes = G.workspace_size(mode="batched", batch=128)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    G.compute(None, workspace=ws, stream=s, mode="batched", batch=128)
+    out = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    G.scores("undirected", out=out)
+    assert_close(out.cpu().numpy() * 2, ref, what="device output")
+    G.close()
