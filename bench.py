@@ -1,0 +1,183 @@
+"""Benchmark: exact betweenness centrality throughput on one MI355X.
+
+One step = one full pass of the hot path over the workload: every source of
+the graph through bc_compute (forward counting sweep, backward dependency
+sweep, score fold), inputs resident in HBM.  The printed JSON line carries
+GTEPS (sources x undirected edges / s), the roofline of the dominant kernel,
+the one-source-per-launch form on a source sample, and the CPU oracle timed
+on the host on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "BC GTEPS (sources×edges/s) batched vs plain, 1 GPU; p50/p99 query latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name: str, sources_arg: int):
+    import graphgen as gg
+    if name == "c1":
+        g, wl, prune = gg.config_c1(), "rmat10_ef16_all_sources", False
+    elif name == "c2":
+        g, wl, prune = gg.config_c2(), "rmat16_ef16_all_sources", False
+    elif name == "c3":
+        g, wl, prune = gg.config_c3(), "rmat20_ef16_plus30pct_pendants_pruned", True
+    elif name == "c4":
+        g, wl, prune = gg.config_c4(), "grid2048_roadlike_8192_sources", False
+        if sources_arg <= 0:
+            sources_arg = 8192
+    else:
+        raise SystemExit(f"unknown config {name}")
+    src = None
+    if sources_arg > 0:
+        src = gg.sample(g.non_isolated(), min(sources_arg, len(g.non_isolated())), 44)
+        wl = wl.replace("all_sources", f"{len(src)}_sampled_sources")
+    return g, wl, prune, src
+
+
+def alg_bytes(n: int, nnz: int, launches: int, st: dict) -> float:
+    """Algorithmic bytes of a run: per launch the CSR streamed once per
+    sweep (2 sweeps) and the score array read and written once; per source
+    a 1-bit level test per directed edge of the reached set per sweep, one
+    8-byte count forward and one 8-byte dependency term backward per DAG
+    edge, and 40 bytes per reached vertex (level 4+4, count 8+8, dependency
+    8+8, each written once and read once)."""
+    per_launch = 2 * (4 * (n + 1) + 4 * nnz) + 16 * n
+    return float(launches * per_launch + 2 * st["reached_nnz"] / 8 + 16 * st["dag_edges"] + 40 * st["reached"])
+
+
+def timed_compute(G, sources, stream, **opts):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    st = G.compute(sources, stream=stream, **opts)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return st, e0.elapsed_time(e1)
+
+
+def cpu_baseline(g, m: int, budget_s: float, seed: int = 91):
+    import graphgen as gg
+    import oracle
+    cores = min(os.cpu_count() or 1, 16)
+    cand = g.non_isolated()
+    probe = gg.sample(cand, min(len(cand), 2 * cores), seed)
+    t0 = time.perf_counter()
+    oracle.bc(g, probe, nthreads=cores)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    k = int(min(len(cand), max(len(probe), len(probe) * budget_s / dt)))
+    S = gg.sample(cand, k, seed + 1)
+    t0 = time.perf_counter()
+    oracle.bc(g, S, nthreads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": k * m / dt / 1e9, "unit": "GTEPS", "cores": cores, "kind": "oracle",
+            "sample": f"{k} uniformly sampled sources of the same graph (seed {seed + 1}), sequential Brandes "
+                      f"per source, static split over {cores} threads; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--sources", type=int, default=0, help="sample this many sources (0 = all)")
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--mode", default="batched")
+    ap.add_argument("--alpha", type=float, default=0.0)
+    ap.add_argument("--grid-per-cu", type=int, default=0)
+    ap.add_argument("--deg2", action="store_true")
+    ap.add_argument("--plain-sample", type=int, default=2048)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        raise SystemExit(2)
+
+    import torch
+    import paper_1602_00963_amd as bcm
+
+    g, wl, prune, sources = workload(args.config, args.sources)
+    n, nnz, m = g.n, g.nnz, g.m
+    log(f"workload {wl}: n={n} m={m}")
+    ctx = bcm.Context(0)
+    G = bcm.Graph(ctx, g, validate=False, prune=prune)
+    stream = torch.cuda.Stream()
+    opts = dict(mode=args.mode, batch=args.batch, deg1=prune, deg2=args.deg2, alpha=args.alpha,
+                grid_per_cu=args.grid_per_cu)
+    for i in range(args.warmup):
+        st, ms = timed_compute(G, sources, stream, **opts)
+        log(f"warmup {i}: {ms:.1f} ms, launches {st['launches']}")
+    times, stats = [], []
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    for i in range(args.steps):
+        st, ms = timed_compute(G, sources, stream, **opts)
+        times.append(ms)
+        stats.append(st)
+        log(f"step {i}: {ms:.1f} ms  {st['te'] / ms / 1e6:.2f} GTEPS  launches {st['launches']} "
+            f"levels {st['levels']} bu {st['bottom_up_levels']} overflowed {st['overflowed']}")
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t_wall) * 1e3
+    st = stats[-1]
+    ms_step = wall_ms / args.steps
+    gteps = st["te"] / (ms_step / 1e3) / 1e9
+    kern_ms = float(np.median(times))
+    per_launch_ms = kern_ms / max(st["launches"], 1)
+    tn = nnz if not prune else G.stats()["residual_nnz"]
+    bytes_run = alg_bytes(n, tn, st["launches"], st)
+    achieved = bytes_run / (kern_ms / 1e3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64+f64", "data": "synthetic",
+        "config": {"workload": wl, "n": n, "m": m, "sources": int(st["sources"]), "traversed": int(st["traversed"]),
+                   "mode": args.mode, "batch": args.batch, "pruned": prune, "deg2": args.deg2},
+        "gteps_2m": round(2 * gteps, 3),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "batch_kernel" if args.mode == "batched" else "plain_kernel",
+                     "avg_launch_ms": round(per_launch_ms, 4), "launches": int(st["launches"]),
+                     "alg_bytes_per_launch": round(bytes_run / max(st["launches"], 1)),
+                     "bytes_per_te": round(bytes_run / st["raw_te"], 3) if st["raw_te"] else None},
+    }
+    if not args.no_plain and args.mode == "batched":
+        import graphgen as gg
+        cand = g.non_isolated() if sources is None else sources
+        ps = gg.sample(cand, min(args.plain_sample, len(cand)), 7)
+        pst, pms = timed_compute(G, ps, stream, mode="plain", deg1=prune)
+        pg = pst["te"] / (pms / 1e3) / 1e9
+        pbytes = alg_bytes(n, tn, pst["launches"], pst)
+        out["plain"] = {"gteps": round(pg, 3), "sample_sources": int(len(ps)), "ms": round(pms, 1),
+                        "avg_launch_ms": round(pms / max(pst["launches"], 1), 4),
+                        "achieved_GBs": round(pbytes / (pms / 1e3) / 1e9, 1)}
+        out["batched_over_plain"] = round(gteps / pg, 2)
+        log(f"plain: {pg:.2f} GTEPS on {len(ps)} sources")
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(g, m, args.cpu_budget)
+        log(f"cpu: {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

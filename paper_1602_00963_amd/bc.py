@@ -74,6 +74,14 @@ def lib():
     """Load libbc.so (raises if it was not built)."""
     global _lib
     if _lib is None:
+        # One HIP runtime per process: torch bundles its own libamdhip64
+        # (same soname as the system one).  Loading torch first makes the
+        # dynamic linker bind libbc to that copy, so torch tensors, streams
+        # and events and this library share one runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1602_00963_amd/build.py")
         L = ctypes.CDLL(LIB_PATH)

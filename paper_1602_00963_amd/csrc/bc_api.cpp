@@ -59,6 +59,7 @@ struct PlainWs {
   Unit* U;
   LevelCtr* lc;
   unsigned long long* stats;
+  GridBar* bar;
   size_t ctl_bytes;  // bytes from `lc` through the control scalars (zeroed per call)
   char* ctl_begin;
 };
@@ -90,6 +91,7 @@ size_t plain_layout(int64_t n, int64_t nnz, char* base, PlainWs* w) {
   t.ovf_count = c.take<int32_t>(1);
   t.ns = c.take<uint64_t>(1);
   t.stats = c.take<unsigned long long>(kStCount);
+  t.bar = c.take<GridBar>(1);
   c.off = align_up(c.off, 256);
   t.ctl_bytes = c.off - ctl0;
   t.ctl_begin = base ? base + ctl0 : nullptr;
@@ -120,6 +122,8 @@ struct BatchWs {
   LevelCtr* lc;
   uint32_t* lane_ovf;
   unsigned long long *lane_ns, *stats, *fulledges;
+  GridBar* bar;
+  size_t mask_bytes;   // vis + fm, cleared per call
   char* tables;        // kTableBatches lane tables
   size_t table_bytes;  // bytes of one table
   size_t ctl_bytes;
@@ -143,8 +147,9 @@ size_t batch_layout(int64_t n, int64_t nnz, int B, int cap_factor, char* base, B
   t.lv = c.take<int32_t>((size_t)n * B);
   t.sig = c.take<uint64_t>((size_t)n * B);
   t.se = c.take<int32_t>((size_t)n * B);
-  t.vis = c.take<uint64_t>((size_t)n * K);
-  t.fm = c.take<uint64_t>((size_t)3 * n * K);
+  t.vis = c.take<uint64_t>((size_t)n * K * 5);  // vis then the four level-mask arrays
+  t.fm = t.vis ? t.vis + (size_t)n * K : nullptr;
+  t.mask_bytes = sizeof(uint64_t) * (size_t)n * K * 5;
   t.stamp = c.take<int32_t>(n);
   t.Q = c.take<int32_t>(t.caps.entries);
   t.U = c.take<Unit>(t.caps.units);
@@ -168,6 +173,7 @@ size_t batch_layout(int64_t n, int64_t nnz, int B, int cap_factor, char* base, B
   t.lane_ns = c.take<unsigned long long>(B);
   t.fulledges = c.take<unsigned long long>(1);
   t.stats = c.take<unsigned long long>(kStCount);
+  t.bar = c.take<GridBar>(1);
   c.off = align_up(c.off, 256);
   t.ctl_bytes = c.off - ctl0;
   t.ctl_begin = base ? base + ctl0 : nullptr;
@@ -604,6 +610,8 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   BatchWs w;
   batch_layout(g->n, g->nnz, r.B, cap_factor, wsbase, &w);
   HIPCHK(hipMemsetAsync(w.ctl_begin, 0, w.ctl_bytes, st));
+  HIPCHK(hipMemsetAsync(w.vis, 0, w.mask_bytes, st));
+  HIPCHK(hipMemsetAsync(w.stamp, 0xff, sizeof(int32_t) * (size_t)g->n, st));
   Packing pk;
   pack_lanes(groups, triples, r.B, &pk);
   if (trace_lane_vertex) trace_lane_vertex->assign(pk.lane_group.begin(), pk.lane_group.end());
@@ -645,6 +653,8 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   a.fail_list = w.fail_list;
   a.fail_count = w.fail_count;
   a.fulledges = w.fulledges;
+  a.bar = w.bar;
+  a.clear_at_end = tr ? 0 : 1;
   a.alpha = r.alpha;
   a.cap_entries = (int32_t)w.caps.entries;
   a.cap_units = (int32_t)w.caps.units;
@@ -728,6 +738,7 @@ bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& t
   a.ovf_count = w.ovf_count;
   a.ns = w.ns;
   a.stats = w.stats;
+  a.bar = w.bar;
   a.bc = bc;
   a.delta_out = delta_out;
   a.alpha = r.alpha;
@@ -869,6 +880,11 @@ void graph_groups(const bc_graph* g, const Resolved& r, const int32_t* sources, 
 
 int64_t graph_n(const bc_graph* g) { return g->n; }
 int context_device(const bc_context* c) { return c->device; }
+int batch_occupancy(int K) {
+  int e = 0, x = 0;
+  if (batch_max_grid(false, K, 256, &e) != hipSuccess || batch_max_grid(true, K, 256, &x) != hipSuccess) return 0;
+  return std::min(e, x);
+}
 int64_t graph_nnz(const bc_graph* g) { return g->nnz; }
 int graph_device(const bc_graph* g) { return g->ctx->device; }
 size_t graph_ws_bytes(const bc_graph* g, const Resolved& r) { return ws_bytes_for(g, r, 32); }

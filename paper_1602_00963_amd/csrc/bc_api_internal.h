@@ -30,5 +30,7 @@ int context_device(const bc_context* c);
 int64_t graph_nnz(const bc_graph* g);
 int graph_device(const bc_graph* g);
 size_t graph_ws_bytes(const bc_graph* g, const Resolved& r);
+// Workgroups per CU the batched kernel can keep resident (both count forms).
+int batch_occupancy(int K);
 
 }  // namespace bcx

@@ -113,6 +113,52 @@ struct LevelCtr {
 // Every workgroup reads a level's counters only after the barrier that ends
 // the phase building that level, so all of them take the same decisions.
 
+// Grid-wide barrier of a cooperative launch, two-level: the workgroups of
+// one residue class of blockIdx mod 8 (the round-robin order in which
+// workgroups are spread over the eight XCDs) meet on their own counter,
+// the last of each class on a top counter, and the very last bumps a
+// generation word the others poll.  Counters return to 0 by themselves;
+// the generation only grows.  Every wave publishes its writes with an
+// agent-scope release fence before arriving and acquires after leaving.
+struct alignas(128) BarSlot {
+  unsigned v;
+  unsigned pad[31];
+};
+struct GridBar {
+  BarSlot xcd[8];
+  BarSlot top;
+  BarSlot gen;
+};
+
+__device__ __forceinline__ void grid_barrier(GridBar* b) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned nb = gridDim.x;
+    const unsigned g = __hip_atomic_load(&b->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned x = blockIdx.x & 7u;
+    const unsigned nx = (nb + 7u - x) / 8u;
+    const unsigned ntop = nb < 8u ? nb : 8u;
+    bool last = false;
+    if (__hip_atomic_fetch_add(&b->xcd[x].v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == nx - 1u) {
+      __hip_atomic_store(&b->xcd[x].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__hip_atomic_fetch_add(&b->top.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == ntop - 1u) {
+        __hip_atomic_store(&b->top.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = true;
+      }
+    }
+    if (last) {
+      __hip_atomic_store(&b->gen.v, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      while (__hip_atomic_load(&b->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 // Errors raised inside a persistent kernel; the host maps them to bc_status.
 enum DevErr : int32_t { kErrNone = 0, kErrCapEntries = 1, kErrCapUnits = 2, kErrCapPartials = 4, kErrCapMulti = 8 };
 

@@ -47,6 +47,7 @@ struct PlainArgs {
   int32_t* ovf_count;
   uint64_t* ns;               // component size accumulator (1-degree own term)
   unsigned long long* stats;  // StatIdx counters
+  GridBar* bar;
   double* bc;
   double* delta_out;          // per-vertex delta of this source (trace), or null
   int32_t src;
@@ -70,7 +71,7 @@ struct BatchArgs {
   double* sm;                 // [n][64K] extended significand (psi overwrites)
   int32_t* se;                // [n][64K] extended exponent
   uint64_t* vis;              // [n][K] lanes that reached the vertex
-  uint64_t* fm;               // [3][n][K] rotating per-level lane masks
+  uint64_t* fm;               // [4][n][K] rotating per-level lane masks
   int32_t* stamp;             // [n] last level the vertex was appended to
   int32_t* Q;
   Unit* U;
@@ -107,6 +108,8 @@ struct BatchArgs {
   int32_t has_derived;        // any lane derived from two partner lanes
   int32_t has_own;            // any lane with pendant sources (component sizes needed)
   unsigned long long* fulledges; // degrees of vertices every edge lane has reached
+  GridBar* bar;
+  int32_t clear_at_end;       // clear masks and stamps before returning (off for traces)
   double alpha;
   int32_t cap_entries, cap_units, cap_parts, cap_multi, cap_levels;
 };

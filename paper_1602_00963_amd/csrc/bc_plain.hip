@@ -19,12 +19,8 @@
 //   1-degree weights of Eq. (5)).  Split vertices combine their per-unit
 //   partial sums in unit order (the last arrival does it), so scores do not
 //   depend on scheduling.
-#include <hip/hip_cooperative_groups.h>
-
 #include "bc_common.h"
 #include "bc_kernels.h"
-
-namespace cg = cooperative_groups;
 
 namespace bcx {
 
@@ -69,7 +65,6 @@ __device__ __forceinline__ void plain_finalize(const PlainArgs& a, int32_t w, do
 
 template <bool EXT>
 __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
-  cg::grid_group grid = cg::this_grid();
   const int lane = lane_id();
   const int wpb = blockDim.x / kWave;
   const int gw = blockIdx.x * wpb + (int)(threadIdx.x / kWave);
@@ -103,7 +98,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
     }
   }
   if (tid == 0) { a.qoff[0] = 0; a.uoff[0] = 0; }
-  grid.sync();
+  grid_barrier(a.bar);
 
   // ---- forward sweep
   int l = 0;
@@ -213,7 +208,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
       }
     }
     if (ballot(wrapped) != 0 && lane == 0) atomicOr(a.ovf_now, 1);
-    grid.sync();
+    grid_barrier(a.bar);
     if (EXT) {
       // counting phase: sigma of the new frontier, pulled from level l
       if (ld_relaxed(&a.lc[nl].err) != 0) { failed = true; break; }
@@ -255,7 +250,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
           }
         }
       }
-      grid.sync();
+      grid_barrier(a.bar);
     }
     l = nl;
     ebase = ebn;
@@ -274,7 +269,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
       if (r3) atomicAdd((unsigned long long*)a.ns, (unsigned long long)r3);
     }
   }
-  grid.sync();
+  grid_barrier(a.bar);
   const bool overflowed = ld_relaxed(a.ovf_now) != 0;
 
   // ---- backward sweep (skipped when counts wrapped: the host reruns the source)
@@ -317,12 +312,12 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
           }
         }
       }
-      grid.sync();
+      grid_barrier(a.bar);
     }
   }
 
   // ---- epilogue: own term of the 1-degree reduction, reset the control block
-  grid.sync();  // nobody reads ovf_now, ns or the level counters past this point
+  grid_barrier(a.bar);  // nobody reads ovf_now, ns or the level counters past this point
   if (tid == 0) {
     if (!failed && !overflowed && a.own > 0) {
       const double ns = (double)*a.ns;

@@ -56,6 +56,7 @@ struct Worker {
 
 struct bc_server {
   int device = 0;
+  int grid_per_cu = 1;  // per batch kernel, so that all in-flight kernels are co-resident
   bc_server_config cfg{};
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -76,6 +77,7 @@ bc_compute_opts serve_opts(const bc_server* s) {
   o.mode = BC_MODE_BATCHED;
   o.batch = s->cfg.batch;
   o.sigma_mode = BC_SIGMA_AUTO;
+  o.grid_per_cu = s->grid_per_cu;
   return o;
 }
 
@@ -126,7 +128,18 @@ bool take_job(bc_server* s, Worker* w, Job* job) {
   const size_t need = graph_ws_bytes(lead->g, r);
   if (w->ws_bytes < need) {
     const int64_t grow = (int64_t)need - (int64_t)w->ws_bytes;
-    if (s->reserved + grow > s->cfg.hbm_budget_bytes) return false;  // wait for memory
+    if (s->reserved + grow > s->cfg.hbm_budget_bytes) {
+      // an idle worker's smaller workspace may be what blocks the growth:
+      // give it back so a worker can grow once the running batches end
+      if (w->ws) {
+        (void)hipFree(w->ws);
+        w->ws = nullptr;
+        s->reserved -= (int64_t)w->ws_bytes;
+        w->ws_bytes = 0;
+        s->cv_work.notify_all();
+      }
+      return false;
+    }
     if (w->ws) (void)hipFree(w->ws);
     w->ws = nullptr;
     s->reserved -= (int64_t)w->ws_bytes;
@@ -217,6 +230,13 @@ bc_status bc_server_create(bc_context* ctx, const bc_server_config* cfg, bc_serv
   if (s->cfg.batch <= 0) s->cfg.batch = 256;
   if (s->cfg.queue_capacity <= 0) s->cfg.queue_capacity = 4096;
   if (s->cfg.batch % 64 || s->cfg.batch > 256) { delete s; return fail(BC_E_INVALID_ARG, "batch must be 64..256, multiple of 64"); }
+  // Persistent kernels wait at grid barriers for all their workgroups, so
+  // kernels running side by side must all fit on the device at once: give
+  // each a 1/max_inflight share of the workgroup slots.
+  const int occ = batch_occupancy(s->cfg.batch / 64);
+  if (occ < 1) { delete s; return fail(BC_E_DEVICE, "occupancy query failed"); }
+  if (s->cfg.max_inflight > occ) s->cfg.max_inflight = occ;
+  s->grid_per_cu = occ / s->cfg.max_inflight;
   for (int i = 0; i < s->cfg.max_inflight; ++i) {
     auto w = std::make_unique<Worker>();
     if (hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking) != hipSuccess) {

@@ -200,12 +200,16 @@ def test_degree2_derivation_equals_unpruned(bcm, ctx, batch):
 
 def test_sources_with_repeats_and_isolated(bcm, ctx):
     g = gg.disjoint_union(gg.rmat(9, 8, 2), gg.complete(1))
-    S = np.array([3, 3, 5, g.n - 1, 7, 3], dtype=np.int32)
+    nz = g.non_isolated()
+    a, b = int(nz[0]), int(nz[1])
+    S = np.array([a, a, b, g.n - 1, 7, a], dtype=np.int32)
     ref, _ = oracle.bc(g, S)
+    deg = g.degrees()
     for opts in MODES[:2]:
         got, st = run_bc(bcm, ctx, g, S, **opts)
         assert_close(got, ref, what=str(opts))
-        assert st["sources"] == 5
+        assert st["sources"] == int(np.sum(deg[S] > 0))
+        assert st["traversed"] == len(set(int(s) for s in S if deg[s] > 0))
 
 
 def test_batched_deterministic(bcm, ctx):
