@@ -74,6 +74,104 @@ def timed_compute(G, sources, stream, **opts):
     return st, e0.elapsed_time(e1)
 
 
+KERNEL_SOURCES = ["paper_1602_00963_amd/csrc/bc_batch.hip", "paper_1602_00963_amd/csrc/bc_common.h",
+                  "paper_1602_00963_amd/csrc/bc_kernels.h"]
+
+
+def kernel_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name: str):
+    """HBM bytes per launch of the batched kernel from committed rocprofv3
+    counter runs (FETCH_SIZE, WRITE_SIZE, each scaled by the same counter on
+    a plain copy of known size); None unless the kernel source is unchanged
+    since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", f"traffic_batch_kernel_{workload_name}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("kernel_sha") != kernel_sha():
+        return None
+    return t
+
+
+def copy_calibration(nbytes: int) -> None:
+    """A plain device-to-device copy of known size, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
+
+
+def serving_run(bcm, ctx, n_graphs: int, max_scale: int, n_queries: int, rho: float, seed: int = 5):
+    """Poisson stream of BC queries over resident graphs through the
+    continuous-batching server: p50/p99 latency and GTEPS.  The arrival rate
+    is rho times the capacity measured first in a closed loop."""
+    import threading
+    import graphgen as gg
+    specs = gg.serving_graph_specs(n_graphs, 5000, 12, max_scale)
+    graphs = [gg.rmat(s, ef, sd) for s, ef, sd in specs]
+    Gs = [bcm.Graph(ctx, g, validate=False) for g in graphs]
+    rng = np.random.default_rng(seed)
+    qs = []
+    for i in range(n_queries):
+        gi = int(rng.integers(len(graphs)))
+        cand = graphs[gi].non_isolated()
+        k = int(min(len(cand), rng.integers(256, 8193)))
+        qs.append((gi, gg.sample(cand, k, 100000 + i)))
+    srv = bcm.Server(ctx, max_inflight=4, batch=256)
+    # closed loop on a prefix: capacity in queries / s
+    warm = qs[: max(8, n_queries // 10)]
+    t0 = time.perf_counter()
+    tk = [srv.submit(Gs[gi], S) for gi, S in warm]
+    for t in tk:
+        srv.wait(t)
+    cap = len(warm) / (time.perf_counter() - t0)
+    rate = rho * cap
+    gaps = rng.exponential(1.0 / rate, size=len(qs))
+    stats = [None] * len(qs)
+    tickets = [None] * len(qs)
+
+    def submitter():
+        nxt = time.perf_counter()
+        for i, (gi, S) in enumerate(qs):
+            nxt += gaps[i]
+            d = nxt - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets[i] = srv.submit(Gs[gi], S)
+
+    th = threading.Thread(target=submitter)
+    t0 = time.perf_counter()
+    th.start()
+    for i in range(len(qs)):
+        while tickets[i] is None:
+            time.sleep(0.0005)
+        stats[i] = srv.wait(tickets[i])
+    th.join()
+    span = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([s["latency_ms"] for s in stats])
+    te = sum(s["te"] for s in stats)
+    for G in Gs:
+        G.close()
+    return {"graphs": len(graphs), "scales": [s for s, _, _ in specs], "queries": len(qs), "rho": rho,
+            "closed_loop_qps": round(cap, 2), "offered_qps": round(rate, 2),
+            "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "gteps": round(te / span / 1e9, 3), "span_s": round(span, 2)}
+
+
 def cpu_baseline(g, m: int, budget_s: float, seed: int = 91):
     import graphgen as gg
     import oracle
@@ -105,11 +203,21 @@ def main():
     ap.add_argument("--alpha", type=float, default=0.0)
     ap.add_argument("--grid-per-cu", type=int, default=0)
     ap.add_argument("--deg2", action="store_true")
+    ap.add_argument("--autotune", type=int, default=0, help="tune batch/alpha/grid on this many sampled sources first")
     ap.add_argument("--plain-sample", type=int, default=2048)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, help="only run a copy of this many bytes")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-graphs", type=int, default=8)
+    ap.add_argument("--serving-max-scale", type=int, default=15)
+    ap.add_argument("--serving-queries", type=int, default=200)
+    ap.add_argument("--serving-rho", type=float, default=0.8)
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         raise SystemExit(2)
@@ -125,6 +233,15 @@ def main():
     stream = torch.cuda.Stream()
     opts = dict(mode=args.mode, batch=args.batch, deg1=prune, deg2=args.deg2, alpha=args.alpha,
                 grid_per_cu=args.grid_per_cu)
+    tuned = None
+    if args.autotune > 0 and args.mode == "batched":
+        import graphgen as gg
+        cand = g.non_isolated() if sources is None else sources
+        t0 = time.perf_counter()
+        tuned = G.autotune(gg.sample(cand, min(args.autotune, len(cand)), 17), deg1=prune, deg2=args.deg2)
+        tuned["seconds"] = round(time.perf_counter() - t0, 2)
+        log(f"autotune: {tuned}")
+        opts.update(batch=0, alpha=0.0, grid_per_cu=0)
     for i in range(args.warmup):
         st, ms = timed_compute(G, sources, stream, **opts)
         log(f"warmup {i}: {ms:.1f} ms, launches {st['launches']}")
@@ -152,15 +269,20 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64+f64", "data": "synthetic",
         "config": {"workload": wl, "n": n, "m": m, "sources": int(st["sources"]), "traversed": int(st["traversed"]),
-                   "mode": args.mode, "batch": args.batch, "pruned": prune, "deg2": args.deg2},
+                   "mode": args.mode, "batch": tuned["batch"] if tuned else args.batch, "pruned": prune,
+                   "deg2": args.deg2, "autotuned": tuned},
         "gteps_2m": round(2 * gteps, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel_sha": kernel_sha(),
                      "kernel": "batch_kernel" if args.mode == "batched" else "plain_kernel",
                      "avg_launch_ms": round(per_launch_ms, 4), "launches": int(st["launches"]),
                      "alg_bytes_per_launch": round(bytes_run / max(st["launches"], 1)),
                      "bytes_per_te": round(bytes_run / st["raw_te"], 3) if st["raw_te"] else None},
     }
+    tr = measured_traffic(wl) if args.mode == "batched" else None
+    if tr:
+        out["roofline"]["traffic"] = round(tr["bytes_per_launch"])
+        out["roofline"]["traffic_source"] = tr["source"]
     if not args.no_plain and args.mode == "batched":
         import graphgen as gg
         cand = g.non_isolated() if sources is None else sources
@@ -173,6 +295,10 @@ def main():
                         "achieved_GBs": round(pbytes / (pms / 1e3) / 1e9, 1)}
         out["batched_over_plain"] = round(gteps / pg, 2)
         log(f"plain: {pg:.2f} GTEPS on {len(ps)} sources")
+    if not args.no_serving:
+        out["serving"] = serving_run(bcm, ctx, args.serving_graphs, args.serving_max_scale, args.serving_queries,
+                                     args.serving_rho)
+        log(f"serving: {out['serving']}")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, m, args.cpu_budget)
         log(f"cpu: {out['cpu_baseline']}")

@@ -111,11 +111,12 @@ enum {
 
 typedef struct bc_compute_opts {
   int32_t mode;         /* BC_MODE_* */
-  int32_t batch;        /* sources per batch, multiple of 64 in [64, 256]; 0 = 256 */
+  int32_t batch;        /* sources per batch, multiple of 64 in [64, 256]; 0 = tuned (bc_autotune) or 256 */
   uint32_t heuristics;  /* BC_H_* */
   int32_t sigma_mode;   /* BC_SIGMA_* */
-  double alpha;         /* bottom-up when frontier edges * alpha > unvisited edges; 0 = default */
-  int32_t block;        /* threads per workgroup (256 or 512); 0 = 256 */
+  double alpha;         /* bottom-up when frontier edges * alpha > unvisited edges; 0 = default
+                           (tuned if available), < 0 = never bottom-up */
+  int32_t block;        /* threads per workgroup: 0 or 256 (the only supported value) */
   int32_t grid_per_cu;  /* workgroups per CU for the persistent grid; 0 = occupancy limit */
 } bc_compute_opts;
 
@@ -153,6 +154,21 @@ typedef struct bc_run_stats {
 bc_status bc_workspace_size(const bc_graph* g, const bc_compute_opts* opts, size_t* bytes);
 bc_status bc_compute(bc_graph* g, const int32_t* sources, int64_t k, const bc_compute_opts* opts,
                      void* workspace, size_t ws_bytes, void* stream, bc_run_stats* stats);
+
+/*
+ * Autotuner for the batched mode: times trial runs of `sample` (k source
+ * ids, at least two batches' worth recommended) into a scratch score array
+ * (the graph's scores are untouched) over batch width {64, 128, 192, 256},
+ * the bottom-up threshold alpha {0 = never, 0.5, 1, 2, 4, 8} and the
+ * persistent grid {occupancy limit, half of it}, by coordinate descent
+ * starting from *opts.  On return *opts holds the fastest setting found
+ * (mode, heuristics and sigma_mode are kept) and *gteps its throughput
+ * (sample sources x m / time).  budget_ms bounds the tuning time (0 = no
+ * bound beyond one pass).  The result is also remembered by the graph and
+ * used by bc_compute calls whose opts->batch is 0.
+ */
+bc_status bc_autotune(bc_graph* g, const int32_t* sample, int64_t k, bc_compute_opts* opts, double budget_ms,
+                      double* gteps);
 
 enum { BC_RAW = 0, BC_UNDIRECTED = 1 };
 /* Copies the accumulated scores (n doubles) into out (host, or device if

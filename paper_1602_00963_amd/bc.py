@@ -28,7 +28,7 @@ RAW, UNDIRECTED = 0, 1
 EXPORTED = ["bc_context_create", "bc_context_destroy", "bc_graph_load", "bc_graph_stats_get", "bc_graph_free",
             "bc_workspace_size", "bc_compute", "bc_scores", "bc_scores_reset", "bc_trace", "bc_validate_csr",
             "bc_prune_deg1_host", "bc_server_create", "bc_server_destroy", "bc_submit", "bc_wait",
-            "bc_status_string", "bc_last_error"]
+            "bc_status_string", "bc_last_error", "bc_autotune"]
 
 
 class GraphStats(ctypes.Structure):
@@ -103,6 +103,7 @@ def lib():
             "bc_server_destroy": [vp],
             "bc_submit": [vp, vp, vp, i64, vp, vp],
             "bc_wait": [vp, ctypes.c_uint64, i64, vp],
+            "bc_autotune": [vp, vp, i64, vp, ctypes.c_double, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -229,6 +230,16 @@ class Graph:
         _check(lib().bc_compute(self.h, _p(src), k, ctypes.byref(o), ws_ptr, ws_bytes, _stream_handle(stream),
                                 ctypes.byref(st)), "bc_compute")
         return st.as_dict()
+
+    def autotune(self, sample, budget_ms: float = 0.0, **opts) -> dict:
+        """Tune the batched mode on `sample` (scores untouched); later
+        compute() calls with batch=0 use the result."""
+        o = make_opts(**opts)
+        src = _i32(sample)
+        gt = ctypes.c_double(0.0)
+        _check(lib().bc_autotune(self.h, _p(src), len(src), ctypes.byref(o), budget_ms, ctypes.byref(gt)),
+               "bc_autotune")
+        return {"batch": o.batch, "alpha": o.alpha, "grid_per_cu": o.grid_per_cu, "gteps": gt.value}
 
     def scores(self, norm: str = "raw", out=None) -> np.ndarray:
         """Accumulated scores; `out` may be a torch float64 device tensor."""

@@ -208,6 +208,10 @@ struct bc_graph {
   // library-owned cached workspace
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // batched-mode setting chosen by bc_autotune
+  bool tuned = false;
+  int32_t tuned_batch = 0, tuned_grid = 0;
+  double tuned_alpha = 0.0;
   std::mutex mu;
 };
 
@@ -417,19 +421,22 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
   if (!o) o = &d;
   r->mode = o->mode;
   if (r->mode != BC_MODE_PLAIN && r->mode != BC_MODE_BATCHED) return fail(BC_E_INVALID_ARG, "unknown mode");
-  r->B = o->batch ? o->batch : 256;
+  r->B = o->batch ? o->batch : (g->tuned ? g->tuned_batch : 256);
   if (r->B % 64 != 0 || r->B < 64 || r->B > 256) return fail(BC_E_INVALID_ARG, "batch must be 64, 128, 192 or 256");
   r->K = r->B / 64;
   r->block = o->block ? o->block : 256;
   if (r->block != 256) return fail(BC_E_INVALID_ARG, "block must be 256");
-  r->grid_per_cu = o->grid_per_cu;
+  r->grid_per_cu = o->grid_per_cu ? o->grid_per_cu : (g->tuned && !o->batch ? g->tuned_grid : 0);
   r->sigma_mode = o->sigma_mode;
   if (r->sigma_mode < 0 || r->sigma_mode > 2) return fail(BC_E_INVALID_ARG, "unknown sigma mode");
   r->deg1 = (o->heuristics & BC_H_DEG1) != 0;
   r->deg2 = (o->heuristics & BC_H_DEG2) != 0;
   if (r->deg1 && !g->pruned) return fail(BC_E_INVALID_ARG, "BC_H_DEG1 needs a graph loaded with BC_LOAD_PRUNE_DEG1");
   if (r->deg2 && r->mode != BC_MODE_BATCHED) return fail(BC_E_INVALID_ARG, "BC_H_DEG2 needs the batched mode");
-  r->alpha = o->alpha > 0 ? o->alpha : (r->mode == BC_MODE_PLAIN ? 4.0 : 2.0);
+  if (o->alpha > 0) r->alpha = o->alpha;
+  else if (o->alpha < 0) r->alpha = 0.0;  // never bottom-up
+  else if (g->tuned && !o->batch && r->mode == BC_MODE_BATCHED) r->alpha = g->tuned_alpha;
+  else r->alpha = r->mode == BC_MODE_PLAIN ? 4.0 : 2.0;
   return BC_OK;
 }
 
@@ -847,10 +854,28 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
   rs.traversed = (int64_t)groups.size() - (int64_t)triples.size();
   rs.derived = (int64_t)triples.size();
   rs.te = (double)credited * (double)(g->nnz / 2);
-  const bool ext0 = r.sigma_mode == BC_SIGMA_EXTENDED;
+  bool ext0 = r.sigma_mode == BC_SIGMA_EXTENDED;
   CallOut co;
-  bc_status s = run_groups(g, r, ext0, tg, groups, triples, workspace, ws_bytes, st, slots, nslots, &co);
-  if (s != BC_OK) return s;
+  bc_status s = BC_OK;
+  std::vector<Group> rest;
+  if (r.mode == BC_MODE_BATCHED && r.sigma_mode == BC_SIGMA_AUTO && triples.empty() &&
+      groups.size() > (size_t)(4 * r.B)) {
+    // probe: one batch in exact form; if most of its sources wrap (long
+    // diameters), the other batches go straight to the extended form
+    std::vector<Group> head(groups.begin(), groups.begin() + r.B);
+    rest.assign(groups.begin() + r.B, groups.end());
+    s = run_groups(g, r, false, tg, head, {}, workspace, ws_bytes, st, slots, nslots, &co);
+    if (s != BC_OK) return s;
+    if (2 * co.ovf.size() > head.size()) ext0 = true;
+    CallOut c2;
+    s = run_groups(g, r, ext0, tg, rest, {}, workspace, ws_bytes, st, slots, nslots, &c2);
+    if (s != BC_OK) return s;
+    for (int i = 0; i < kStCount; ++i) co.st[i] += c2.st[i];
+    co.ovf.insert(co.ovf.end(), c2.ovf.begin(), c2.ovf.end());
+  } else {
+    s = run_groups(g, r, ext0, tg, groups, triples, workspace, ws_bytes, st, slots, nslots, &co);
+    if (s != BC_OK) return s;
+  }
   add_stats(&rs, co);
   std::vector<int32_t> ov = co.ovf;
   std::sort(ov.begin(), ov.end());
@@ -936,6 +961,82 @@ bc_status bc_scores_reset(bc_graph* g) {
   if (!g) return fail(BC_E_INVALID_ARG, "null graph");
   HIPCHK(hipSetDevice(g->ctx->device));
   HIPCHK(hipMemset(g->d_bc, 0, sizeof(double) * g->n));
+  return BC_OK;
+}
+
+bc_status bc_autotune(bc_graph* g, const int32_t* sample, int64_t k, bc_compute_opts* opts, double budget_ms,
+                      double* gteps) {
+  if (!g || !sample || k <= 0 || !opts) return fail(BC_E_INVALID_ARG, "bad arguments");
+  for (int64_t i = 0; i < k; ++i)
+    if (sample[i] < 0 || sample[i] >= g->n) return fail(BC_E_INVALID_ARG, "source id out of range");
+  std::lock_guard<std::mutex> lk(g->mu);
+  HIPCHK(hipSetDevice(g->ctx->device));
+  bc_compute_opts base = *opts;
+  base.mode = BC_MODE_BATCHED;
+  Resolved r0;
+  bc_status s = resolve(g, &base, &r0);
+  if (s != BC_OK) return s;
+  std::vector<Group> groups;
+  int64_t credited = 0;
+  map_sources(g->n, g->h_rp.data(), r0.deg1 ? &g->pr : nullptr, sample, k, &groups, &credited);
+  if (groups.empty()) return fail(BC_E_INVALID_ARG, "sample has no non-isolated source");
+  double* scratch = nullptr;
+  HIPCHK(hipMalloc((void**)&scratch, sizeof(double) * g->n));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const auto t_start = std::chrono::steady_clock::now();
+  auto elapsed = [&] {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  };
+  auto trial = [&](const bc_compute_opts& o, double* ms) -> bc_status {
+    Resolved r;
+    bc_status st = resolve(g, &o, &r);
+    if (st != BC_OK) return st;
+    std::vector<Group> gr = groups;
+    double* slots[1] = {scratch};
+    HIPCHK(hipEventRecord(e0, nullptr));
+    st = compute_groups(g, r, gr, credited, nullptr, 0, nullptr, slots, 1, nullptr);
+    HIPCHK(hipEventRecord(e1, nullptr));
+    HIPCHK(hipEventSynchronize(e1));
+    float f = 0.f;
+    HIPCHK(hipEventElapsedTime(&f, e0, e1));
+    *ms = f;
+    return st;
+  };
+  bc_compute_opts best = base;
+  if (!best.batch) best.batch = 256;
+  best.grid_per_cu = 0;
+  double best_ms = 0.0;
+  s = trial(best, &best_ms);             // warms allocations
+  if (s == BC_OK) s = trial(best, &best_ms);
+  auto consider = [&](bc_compute_opts o) {
+    if (s != BC_OK || (budget_ms > 0 && elapsed() > budget_ms)) return;
+    double ms = 0.0;
+    bc_status st = trial(o, &ms);
+    if (st == BC_OK && ms < best_ms) { best = o; best_ms = ms; }
+    if (st != BC_OK && st != BC_E_CAPACITY) s = st;
+  };
+  for (int B : {64, 128, 192, 256}) { bc_compute_opts o = best; o.batch = B; if (B != best.batch) consider(o); }
+  for (double al : {-1.0, 0.5, 1.0, 2.0, 4.0, 8.0}) { bc_compute_opts o = best; o.alpha = al; consider(o); }
+  {
+    int occ = 0;
+    if (batch_max_grid(false, best.batch / 64, 256, &occ) == hipSuccess && occ > 1) {
+      bc_compute_opts o = best;
+      o.grid_per_cu = occ / 2;
+      consider(o);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(scratch);
+  if (s != BC_OK) return s;
+  g->tuned = true;
+  g->tuned_batch = best.batch;
+  g->tuned_alpha = best.alpha > 0 ? best.alpha : (best.alpha < 0 ? 0.0 : 2.0);
+  g->tuned_grid = best.grid_per_cu;
+  *opts = best;
+  if (gteps) *gteps = (double)credited * (double)(g->nnz / 2) / (best_ms * 1e-3) / 1e9;
   return BC_OK;
 }
 

@@ -81,7 +81,7 @@ __device__ __forceinline__ void count_unit(const BatchArgs& a, const Unit& un, c
   const int lane = lane_id();
   const int32_t* __restrict__ rp = a.rp;
   const int32_t* __restrict__ ci = a.ci;
-  const int32_t w = a.Q[un.e];
+  const int32_t w = un.v;
   const int32_t rb = rp[w], re = rp[w + 1];
   const int32_t beg = rb + un.c * CHB;
   const int32_t end = min(re, beg + CHB);
@@ -131,10 +131,8 @@ __device__ __forceinline__ void count_unit(const BatchArgs& a, const Unit& un, c
               if (ti[i] >= 0) {
                 const int32_t v = rl32(vl, ti[i]);
                 const uint64_t mv = rl64(ml[k], ti[i]);
-                if ((mv >> lane) & 1ull) {
-                  const size_t idx = (size_t)v * B + 64 * k + lane;
-                  xs[i] = Ext{a.sm[idx], a.se[idx]};
-                }
+                const size_t row = (size_t)v * B + 64 * k;  // uniform: scalar base + lane offset
+                if ((mv >> lane) & 1ull) xs[i] = Ext{(a.sm + row)[lane], (a.se + row)[lane]};
               }
             }
 #pragma unroll
@@ -147,7 +145,8 @@ __device__ __forceinline__ void count_unit(const BatchArgs& a, const Unit& un, c
               if (ti[i] >= 0) {
                 const int32_t v = rl32(vl, ti[i]);
                 const uint64_t mv = rl64(ml[k], ti[i]);
-                if ((mv >> lane) & 1ull) ys[i] = a.sig[(size_t)v * B + 64 * k + lane];
+                const uint64_t* row = a.sig + (size_t)v * B + 64 * k;  // uniform base, lane offset
+                if ((mv >> lane) & 1ull) ys[i] = row[lane];
               }
             }
 #pragma unroll
@@ -253,7 +252,7 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const Unit& un
   const int32_t* __restrict__ rp = a.rp;
   const int32_t* __restrict__ ci = a.ci;
   double* psi = EXT ? a.sm : (double*)a.sig;
-  const int32_t w = a.Q[un.e];
+  const int32_t w = un.v;
   const int32_t rb = rp[w], re = rp[w + 1];
   uint64_t om[K];
   bool anyo = false;
@@ -305,10 +304,10 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const Unit& un
             if (ti[i] >= 0) {
               const int32_t v = rl32(vl, ti[i]);
               const uint64_t mv = rl64(ml[k], ti[i]);
+              const size_t row = (size_t)v * B + 64 * k;  // uniform base, lane offset
               if ((mv >> lane) & 1ull) {
-                const size_t idx = (size_t)v * B + 64 * k + lane;
-                ys[i] = psi[idx];
-                if (EXT) ys[i] = ldexp(ys[i], ew[k] - a.se[idx]);
+                ys[i] = (psi + row)[lane];
+                if (EXT) ys[i] = ldexp(ys[i], ew[k] - (a.se + row)[lane]);
               }
             }
           }
@@ -464,7 +463,7 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchArgs a) {
     if (!bu) {
       for (int32_t u = ubase + gw; u < ubn; u += nw) {
         const Unit un = a.U[u];
-        const int32_t v = a.Q[un.e];
+        const int32_t v = un.v;
         uint64_t cm[K];
         bool any = false;
 #pragma unroll

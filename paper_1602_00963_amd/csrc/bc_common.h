@@ -88,13 +88,13 @@ __device__ __forceinline__ Ext ext_norm(Ext a) {
 
 // ------------------------------------------------------------ work records
 
-// One unit of edge work: chunk `c` (edges [c*CH, (c+1)*CH) of the entry's
-// adjacency) of level-list entry `e`.  Entries whose adjacency spans several
-// chunks ("split" entries) also carry `mi`, a run-unique index of their
-// arrival counter, and `pb`, the level-relative base of their partial-sum
-// slots; single-chunk entries have mi = -1.
+// One unit of edge work: chunk `c` (edges [c*CH, (c+1)*CH) of the
+// adjacency) of the level-list entry for vertex `v`.  Entries whose
+// adjacency spans several chunks ("split" entries) also carry `mi`, a
+// run-unique index of their arrival counter, and `pb`, the level-relative
+// base of their partial-sum slots; single-chunk entries have mi = -1.
 struct Unit {
-  int32_t e;
+  int32_t v;
   int32_t c;
   int32_t mi;
   int32_t pb;
@@ -225,7 +225,7 @@ __device__ __forceinline__ int append_entries(const Lists& L, int lvl, int32_t e
     } else {
       L.Q[e] = vtx;
       if (nunits == 1) {
-        L.U[u] = Unit{(int32_t)e, 0, -1, 0};
+        L.U[u] = Unit{vtx, 0, -1, 0};
       } else {
         const int32_t mi = atomicAdd(L.gmulti, 1);
         const int32_t pb = atomicAdd(&L.lc[lvl].pslots, nunits);
@@ -236,7 +236,7 @@ __device__ __forceinline__ int append_entries(const Lists& L, int lvl, int32_t e
           raise_err(L, lvl, kErrCapPartials);
         } else {
           L.arrive[mi] = 0;
-          for (int32_t c = 0; c < nunits; ++c) L.U[u + c] = Unit{(int32_t)e, c, mi, pb};
+          for (int32_t c = 0; c < nunits; ++c) L.U[u + c] = Unit{vtx, c, mi, pb};
         }
       }
     }

@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
       // top-down: one wave per unit of the frontier
       for (int32_t u = ubase + gw; u < ubase + nu; u += nw) {
         const Unit un = a.U[u];
-        const int32_t v = a.Q[un.e];
+        const int32_t v = un.v;
         const int32_t beg = rp[v] + un.c * CHP;
         const int32_t end = min(rp[v + 1], beg + CHP);
         const int32_t off = beg + lane;
@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
       const int32_t nu2 = (int32_t)(pk2 & 0xffffffffull);
       for (int32_t u = ubn + gw; u < ubn + nu2; u += nw) {
         const Unit un = a.U[u];
-        const int32_t w = a.Q[un.e];
+        const int32_t w = un.v;
         const int32_t beg = a.rp[w] + un.c * CHP;
         const int32_t end = min(rp[w + 1], beg + CHP);
         const int32_t off = beg + lane;
@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
       const int32_t ub = a.uoff[lb], ue = a.uoff[lb + 1];
       for (int32_t u = ub + gw; u < ue; u += nw) {
         const Unit un = a.U[u];
-        const int32_t w = a.Q[un.e];
+        const int32_t w = un.v;
         double t = 0.0;
         if (lb < depth) {
           const int32_t beg = rp[w] + un.c * CHP;

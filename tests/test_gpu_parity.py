@@ -264,3 +264,29 @@ def test_device_score_output_and_workspace(bcm, ctx):
     G.scores("undirected", out=out)
     assert_close(out.cpu().numpy() * 2, ref, what="device output")
     G.close()
+
+
+def test_autotune_leaves_scores_and_results_unchanged(bcm, ctx):
+    g = gg.rmat(11, 16, 12)
+    G = bcm.Graph(ctx, g)
+    S = gg.sample(g.non_isolated(), 300, 5)
+    tuned = G.autotune(S, budget_ms=20000)
+    assert tuned["batch"] in (64, 128, 192, 256) and tuned["gteps"] > 0
+    assert not G.scores().any()                 # tuning used scratch scores
+    G.compute(S, batch=0)                       # the tuned setting
+    ref, _ = oracle.bc(g, S)
+    assert_close(G.scores(), ref, what="tuned")
+    G.close()
+
+
+def test_long_diameter_lattice_auto_mode(bcm, ctx):
+    """A 64 x 64 road-like lattice, every source, automatic count form: most
+    sources wrap uint64, so after the probe batch the rest run in extended
+    form; scores match the oracle (long-double reruns)."""
+    g = gg.road_grid(64, 64, 0.05, 0.01, 9)
+    say("case lattice auto")
+    ref, ovf = oracle.bc(g, nthreads=8)
+    assert ovf.mean() > 0.5
+    got, st = run_bc(bcm, ctx, g, mode="batched", batch=64)
+    assert st["overflowed"] > 0
+    assert_close(got, ref, what="lattice auto")
