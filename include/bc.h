@@ -115,7 +115,7 @@ typedef struct bc_compute_opts {
   uint32_t heuristics;  /* BC_H_* */
   int32_t sigma_mode;   /* BC_SIGMA_* */
   double alpha;         /* bottom-up when frontier edges * alpha > unvisited edges; 0 = default
-                           (tuned if available), < 0 = never bottom-up */
+                           (tuned if available, else 1 batched / 4 plain), < 0 = never bottom-up */
   int32_t block;        /* threads per workgroup: 0 or 256 (the only supported value) */
   int32_t grid_per_cu;  /* workgroups per CU for the persistent grid; 0 = occupancy limit */
 } bc_compute_opts;

@@ -436,11 +436,12 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
   if (o->alpha > 0) r->alpha = o->alpha;
   else if (o->alpha < 0) r->alpha = 0.0;  // never bottom-up
   else if (g->tuned && !o->batch && r->mode == BC_MODE_BATCHED) r->alpha = g->tuned_alpha;
-  else r->alpha = r->mode == BC_MODE_PLAIN ? 4.0 : 2.0;
+  else r->alpha = r->mode == BC_MODE_PLAIN ? 4.0 : 1.0;
   return BC_OK;
 }
 
 size_t ws_bytes_for(const bc_graph* g, const Resolved& r, int cap_factor) {
+  cap_factor = std::max(cap_factor, r.cap_factor);
   if (r.mode == BC_MODE_PLAIN) return plain_layout(g->n, g->nnz, nullptr, nullptr);
   return batch_layout(g->n, g->nnz, r.B, cap_factor, nullptr, nullptr);
 }
@@ -814,22 +815,31 @@ static bc_status run_groups(bc_graph* g, const Resolved& r, bool ext, const Trav
                             const std::vector<Group>& groups, const std::vector<Triple>& triples, void* user_ws,
                             size_t user_bytes, hipStream_t st, double* const* slots, int nslots, CallOut* out) {
   char* ws = nullptr;
-  bc_status s = get_ws(g, ws_bytes_for(g, r, 32), user_ws, user_bytes, &ws);
+  bc_status s = get_ws(g, ws_bytes_for(g, r, r.cap_factor), user_ws, user_bytes, &ws);
   if (s != BC_OK) return s;
   if (r.mode == BC_MODE_PLAIN) {
     s = run_plain(g, r, ext, tg, groups, ws, st, slots[0], nullptr, out);
     if (s == BC_OK && out->err) return fail(BC_E_CAPACITY, "level-list capacity exceeded");
     return s;
   }
-  s = run_batched(g, r, ext, tg, groups, triples, ws, 32, st, slots, nslots, nullptr, out, nullptr);
+  s = run_batched(g, r, ext, tg, groups, triples, ws, r.cap_factor, st, slots, nslots, nullptr, out, nullptr);
   if (s != BC_OK || out->fail.empty()) return s;
   if (user_ws) return fail(BC_E_CAPACITY, "level-list capacity exceeded; some batches added nothing");
-  // rerun the failed batches' sources without derivation, with lists sized for the worst case
+  // rerun the failed batches' sources without derivation, with lists sized
+  // for the worst case (n * B entries); if that would not fit 32-bit list
+  // indices, with narrower batches
   std::vector<Group> again = groups_at(g->n, groups, out->fail);
-  s = get_ws(g, ws_bytes_for(g, r, r.B), nullptr, 0, &ws);
+  Resolved r2 = r;
+  while (r2.B > 64 && (int64_t)g->n * r2.B + 1024 > (int64_t)INT32_MAX / 2) {
+    r2.B /= 2;
+    r2.K = r2.B / 64;
+  }
+  if ((int64_t)g->n * r2.B + 1024 > (int64_t)INT32_MAX / 2)
+    return fail(BC_E_CAPACITY, "graph too large for worst-case level lists");
+  s = get_ws(g, ws_bytes_for(g, r2, r2.B), nullptr, 0, &ws);
   if (s != BC_OK) return s;
   CallOut o2;
-  s = run_batched(g, r, ext, tg, again, {}, ws, r.B, st, slots, nslots, nullptr, &o2, nullptr);
+  s = run_batched(g, r2, ext, tg, again, {}, ws, r2.B, st, slots, nslots, nullptr, &o2, nullptr);
   if (s != BC_OK) return s;
   if (!o2.fail.empty()) return fail(BC_E_CAPACITY, "level-list capacity exceeded at worst-case size");
   for (int i = 0; i < kStCount; ++i) out->st[i] += o2.st[i];
@@ -912,7 +922,7 @@ int batch_occupancy(int K) {
 }
 int64_t graph_nnz(const bc_graph* g) { return g->nnz; }
 int graph_device(const bc_graph* g) { return g->ctx->device; }
-size_t graph_ws_bytes(const bc_graph* g, const Resolved& r) { return ws_bytes_for(g, r, 32); }
+size_t graph_ws_bytes(const bc_graph* g, const Resolved& r) { return ws_bytes_for(g, r, r.cap_factor); }
 
 }  // namespace bcx
 
@@ -1033,7 +1043,7 @@ bc_status bc_autotune(bc_graph* g, const int32_t* sample, int64_t k, bc_compute_
   if (s != BC_OK) return s;
   g->tuned = true;
   g->tuned_batch = best.batch;
-  g->tuned_alpha = best.alpha > 0 ? best.alpha : (best.alpha < 0 ? 0.0 : 2.0);
+  g->tuned_alpha = best.alpha > 0 ? best.alpha : (best.alpha < 0 ? 0.0 : 1.0);
   g->tuned_grid = best.grid_per_cu;
   *opts = best;
   if (gteps) *gteps = (double)credited * (double)(g->nnz / 2) / (best_ms * 1e-3) / 1e9;

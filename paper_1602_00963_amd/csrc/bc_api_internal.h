@@ -18,6 +18,7 @@ struct Resolved {
   int mode, B, K, block, grid_per_cu, sigma_mode;
   bool deg1, deg2;
   double alpha;
+  int cap_factor = 32;  // batched level-list capacity: n * min(B, cap_factor) entries
 };
 bc_status resolve_opts(const bc_graph* g, const bc_compute_opts* o, Resolved* r);
 void graph_groups(const bc_graph* g, const Resolved& r, const int32_t* sources, int64_t k, std::vector<Group>* groups,

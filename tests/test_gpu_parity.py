@@ -280,10 +280,10 @@ def test_autotune_leaves_scores_and_results_unchanged(bcm, ctx):
 
 
 def test_long_diameter_lattice_auto_mode(bcm, ctx):
-    """A 64 x 64 road-like lattice, every source, automatic count form: most
-    sources wrap uint64, so after the probe batch the rest run in extended
-    form; scores match the oracle (long-double reruns)."""
-    g = gg.road_grid(64, 64, 0.05, 0.01, 9)
+    """A 96 x 96 road-like lattice, every source, automatic count form: about
+    90% of sources wrap uint64, so after the probe batch the rest run in
+    extended form; scores match the oracle (long-double reruns)."""
+    g = gg.road_grid(96, 96, 0.05, 0.01, 9)
     say("case lattice auto")
     ref, ovf = oracle.bc(g, nthreads=8)
     assert ovf.mean() > 0.5

@@ -98,8 +98,11 @@ def test_admission_budget_and_rejection(bcm, ctx):
     ws_small = Gs.workspace_size(mode="batched", batch=64)
     ws_big = Gb.workspace_size(mode="batched", batch=64)
     assert ws_big > 2 * ws_small
-    # budget fits the small graph's workspace plus a few result arrays, not the big one
-    budget = ws_small + 64 * g_small.n * 8
+    # budget fits the small graph's worst-case workspace (the server sizes its
+    # level lists for n * batch entries, at most twice the default) plus a
+    # few result arrays, not the 16x larger graph's
+    budget = 3 * ws_small + 64 * g_small.n * 8
+    assert ws_big > budget
     srv = bcm.Server(ctx, hbm_budget_bytes=budget, max_inflight=2, batch=64)
     S = gg.sample(g_small.non_isolated(), 100, 3)
     tk = [srv.submit(Gs, S) for _ in range(6)]
