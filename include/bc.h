@@ -111,12 +111,12 @@ enum {
 
 typedef struct bc_compute_opts {
   int32_t mode;         /* BC_MODE_* */
-  int32_t batch;        /* sources per batch, multiple of 64 in [64, 256]; 0 = tuned (bc_autotune) or 256 */
+  int32_t batch;        /* sources per batch, multiple of 64 in [64, 1024]; 0 = tuned (bc_autotune) or 256 */
   uint32_t heuristics;  /* BC_H_* */
   int32_t sigma_mode;   /* BC_SIGMA_* */
   double alpha;         /* bottom-up when frontier edges * alpha > unvisited edges; 0 = default
                            (tuned if available, else 1 batched / 4 plain), < 0 = never bottom-up */
-  int32_t block;        /* threads per workgroup: 0 or 256 (the only supported value) */
+  int32_t block;        /* threads per workgroup: 0, or the mode's fixed size (512 batched, 256 plain) */
   int32_t grid_per_cu;  /* workgroups per CU for the persistent grid; 0 = occupancy limit */
 } bc_compute_opts;
 
@@ -158,7 +158,7 @@ bc_status bc_compute(bc_graph* g, const int32_t* sources, int64_t k, const bc_co
 /*
  * Autotuner for the batched mode: times trial runs of `sample` (k source
  * ids, at least two batches' worth recommended) into a scratch score array
- * (the graph's scores are untouched) over batch width {64, 128, 192, 256},
+ * (the graph's scores are untouched) over batch width {64, 128, 256, 512, 1024},
  * the bottom-up threshold alpha {0 = never, 0.5, 1, 2, 4, 8} and the
  * persistent grid {occupancy limit, half of it}, by coordinate descent
  * starting from *opts.  On return *opts holds the fastest setting found

@@ -103,27 +103,33 @@ struct BatchCaps {
   int64_t entries, units, parts, multi;
 };
 
+// Level-list capacities of the batched kernel.  A (vertex, word) entry sits
+// on at most min(64, depth + 1) levels (one per distinct distance of the
+// word's sources); lists are sized for min(64, cap_factor) of them, and a
+// batch that runs out is rerun with the worst case.
 BatchCaps batch_caps(int64_t n, int64_t nnz, int B, int cap_factor) {
-  const int64_t f = std::min<int64_t>(B, cap_factor);
+  const int64_t K = B / 64;
+  const int64_t f = std::min<int64_t>(64, cap_factor);
   BatchCaps c;
-  c.entries = std::min<int64_t>((int64_t)n * f + 1024, (int64_t)INT32_MAX / 2);
-  c.units = std::min<int64_t>(c.entries + nnz * f / kBatchChunk + 1024, (int64_t)INT32_MAX / 2);
-  c.parts = 2 * nnz / kBatchChunk + 1024;
+  c.entries = std::min<int64_t>(n * K * f + 1024, (int64_t)INT32_MAX / 2);
+  c.units = std::min<int64_t>(c.entries + nnz * K * f / kBatchChunk + 1024, (int64_t)INT32_MAX / 2);
+  c.parts = std::min<int64_t>(K * (2 * nnz / kBatchChunk) + 1024, (int64_t)INT32_MAX / 2);  // per level
   c.multi = c.entries;
   return c;
 }
 
 struct BatchWs {
-  int32_t *lv, *se, *stamp, *Q, *qoff, *uoff, *part_e, *arrive, *gmulti, *err, *ovf_list, *ovf_count;
+  int32_t *lv, *se, *qoff, *uoff, *part_e, *arrive, *err, *ovf_list, *ovf_count;
   int32_t *fail_list, *fail_count;
-  uint64_t *sig, *vis, *fm;
-  double *part_m;
+  uint64_t *sig, *vis, *fm, *Q;
+  double *part_m, *pair_bc;
   Unit* U;
   LevelCtr* lc;
   uint32_t* lane_ovf;
   unsigned long long *lane_ns, *stats, *fulledges;
   GridBar* bar;
   size_t mask_bytes;   // vis + fm, cleared per call
+  int32_t cap_pairs;   // (word, slot) pair arrays
   char* tables;        // kTableBatches lane tables
   size_t table_bytes;  // bytes of one table
   size_t ctl_bytes;
@@ -132,14 +138,20 @@ struct BatchWs {
 };
 
 // One batch's lane table: lane_src[B], lane_own[B], l0[B] (int32), lane_w[B]
-// (double), lane_pa[B], lane_pb[B], lane_slot[B] (int8), then 8-aligned
-// edge_lanes[4] (uint64) and slot_bc[64] (device pointers).
+// (double), lane_pair[B] (int16), lane_pa[B], lane_pb[B], lane_slot[B]
+// (int8), pair_slot[kMaxPairs] (int8), then 8-aligned edge_lanes[16]
+// (uint64) and slot_bc[64] (device pointers).
 constexpr int kMaxSlots = 64;
+constexpr int kMaxPairs = kMaxWords + kMaxSlots;
 size_t table_bytes(int B) {
-  return align_up((size_t)B * (4 + 4 + 4 + 8 + 1 + 1 + 1) + 8 + 8 * 4 + 8 * kMaxSlots, 256);
+  return align_up((size_t)B * (4 + 4 + 4 + 8 + 2 + 1 + 1 + 1) + kMaxPairs + 8 + 8 * kMaxWords + 8 * kMaxSlots, 256);
 }
 
-size_t batch_layout(int64_t n, int64_t nnz, int B, int cap_factor, char* base, BatchWs* w) {
+// Lanes are packed slot by slot, so the slots met along the words are
+// non-decreasing and a batch has at most K + slots - 1 (word, slot) pairs.
+int32_t cap_pairs_for(int K, int max_slots) { return K + std::min(max_slots, kMaxSlots) - 1; }
+
+size_t batch_layout(int64_t n, int64_t nnz, int B, int cap_factor, int max_slots, char* base, BatchWs* w) {
   const int K = B / 64;
   Carve c{base};
   BatchWs t{};
@@ -150,14 +162,15 @@ size_t batch_layout(int64_t n, int64_t nnz, int B, int cap_factor, char* base, B
   t.vis = c.take<uint64_t>((size_t)n * K * 5);  // vis then the four level-mask arrays
   t.fm = t.vis ? t.vis + (size_t)n * K : nullptr;
   t.mask_bytes = sizeof(uint64_t) * (size_t)n * K * 5;
-  t.stamp = c.take<int32_t>(n);
-  t.Q = c.take<int32_t>(t.caps.entries);
+  t.Q = c.take<uint64_t>(t.caps.entries);
   t.U = c.take<Unit>(t.caps.units);
   t.qoff = c.take<int32_t>(n + 3);
   t.uoff = c.take<int32_t>(n + 3);
-  t.part_m = c.take<double>((size_t)t.caps.parts * K * 64);
-  t.part_e = c.take<int32_t>((size_t)t.caps.parts * K * 64);
-  t.arrive = c.take<int32_t>(t.caps.multi);
+  t.part_m = c.take<double>((size_t)t.caps.parts * 64);
+  t.part_e = c.take<int32_t>((size_t)t.caps.parts * 64);
+  t.arrive = c.take<int32_t>(t.caps.entries);
+  t.cap_pairs = cap_pairs_for(K, max_slots);
+  t.pair_bc = c.take<double>((size_t)t.cap_pairs * n);
   t.ovf_list = c.take<int32_t>(n + 1);
   t.fail_list = c.take<int32_t>(n + 1);
   t.table_bytes = table_bytes(B);
@@ -165,7 +178,6 @@ size_t batch_layout(int64_t n, int64_t nnz, int B, int cap_factor, char* base, B
   c.off = align_up(c.off, 256);
   const size_t ctl0 = c.off;
   t.lc = c.take<LevelCtr>(n + 3);
-  t.gmulti = c.take<int32_t>(1);
   t.err = c.take<int32_t>(1);
   t.ovf_count = c.take<int32_t>(1);
   t.fail_count = c.take<int32_t>(1);
@@ -422,10 +434,12 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
   r->mode = o->mode;
   if (r->mode != BC_MODE_PLAIN && r->mode != BC_MODE_BATCHED) return fail(BC_E_INVALID_ARG, "unknown mode");
   r->B = o->batch ? o->batch : (g->tuned ? g->tuned_batch : 256);
-  if (r->B % 64 != 0 || r->B < 64 || r->B > 256) return fail(BC_E_INVALID_ARG, "batch must be 64, 128, 192 or 256");
+  if (r->B % 64 != 0 || r->B < 64 || r->B > 64 * kMaxWords)
+    return fail(BC_E_INVALID_ARG, "batch must be a multiple of 64 from 64 to 1024");
   r->K = r->B / 64;
-  r->block = o->block ? o->block : 256;
-  if (r->block != 256) return fail(BC_E_INVALID_ARG, "block must be 256");
+  const int blk = r->mode == BC_MODE_BATCHED ? kBatchBlock : 256;
+  r->block = o->block ? o->block : blk;
+  if (r->block != blk) return fail(BC_E_INVALID_ARG, "block must be 512 (batched) or 256 (plain)");
   r->grid_per_cu = o->grid_per_cu ? o->grid_per_cu : (g->tuned && !o->batch ? g->tuned_grid : 0);
   r->sigma_mode = o->sigma_mode;
   if (r->sigma_mode < 0 || r->sigma_mode > 2) return fail(BC_E_INVALID_ARG, "unknown sigma mode");
@@ -443,7 +457,7 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
 size_t ws_bytes_for(const bc_graph* g, const Resolved& r, int cap_factor) {
   cap_factor = std::max(cap_factor, r.cap_factor);
   if (r.mode == BC_MODE_PLAIN) return plain_layout(g->n, g->nnz, nullptr, nullptr);
-  return batch_layout(g->n, g->nnz, r.B, cap_factor, nullptr, nullptr);
+  return batch_layout(g->n, g->nnz, r.B, cap_factor, r.max_slots, nullptr, nullptr);
 }
 
 struct TravGraph {
@@ -465,7 +479,7 @@ static TravGraph trav(const bc_graph* g, bool deg1) {
 
 static int grid_for(const bc_graph* g, const Resolved& r, bool ext, bool batched) {
   int bpc = 1;
-  hipError_t e = batched ? batch_max_grid(ext, r.K, r.block, &bpc) : plain_max_grid(ext, r.block, &bpc);
+  hipError_t e = batched ? batch_max_grid(ext, r.block, &bpc) : plain_max_grid(ext, r.block, &bpc);
   if (e != hipSuccess || bpc < 1) bpc = 1;
   int want = r.grid_per_cu > 0 ? r.grid_per_cu : (batched ? bpc : 1);
   return g->ctx->cus * std::min(want, bpc);
@@ -493,16 +507,22 @@ static void pack_lanes(const std::vector<Group>& groups, const std::vector<Tripl
       while (lanes.size() % 64) { lanes.push_back(-1); pa.push_back(-1); pb.push_back(-1); }
     }
   };
-  for (const auto& t : triples) {
-    pad_to_word(3);
-    const int base = (int)(lanes.size() % 64);
-    lanes.push_back(t.a); pa.push_back(-1); pb.push_back(-1);
-    lanes.push_back(t.b); pa.push_back(-1); pb.push_back(-1);
-    lanes.push_back(t.c); pa.push_back((int8_t)base); pb.push_back((int8_t)(base + 1));
-  }
-  for (size_t i = 0; i < groups.size(); ++i) {
-    if (in_triple[i]) continue;
-    lanes.push_back((int32_t)i); pa.push_back(-1); pb.push_back(-1);
+  // slot by slot (a triple's members share one slot): its triples, then its other groups
+  int nslot = 1;
+  for (const auto& gr : groups) nslot = std::max(nslot, gr.slot + 1);
+  for (int sl = 0; sl < nslot; ++sl) {
+    for (const auto& t : triples) {
+      if (groups[t.c].slot != sl) continue;
+      pad_to_word(3);
+      const int base = (int)(lanes.size() % 64);
+      lanes.push_back(t.a); pa.push_back(-1); pb.push_back(-1);
+      lanes.push_back(t.b); pa.push_back(-1); pb.push_back(-1);
+      lanes.push_back(t.c); pa.push_back((int8_t)base); pb.push_back((int8_t)(base + 1));
+    }
+    for (size_t i = 0; i < groups.size(); ++i) {
+      if (in_triple[i] || groups[i].slot != sl) continue;
+      lanes.push_back((int32_t)i); pa.push_back(-1); pb.push_back(-1);
+    }
   }
   while (lanes.size() % B) { lanes.push_back(-1); pa.push_back(-1); pb.push_back(-1); }
   p->lane_group = std::move(lanes);
@@ -515,7 +535,8 @@ static void pack_lanes(const std::vector<Group>& groups, const std::vector<Tripl
 struct TablePtrs {
   int32_t *lane_src, *lane_own, *l0;
   double* lane_w;
-  int8_t *pa, *pb, *slot;
+  int16_t* pair;
+  int8_t *pa, *pb, *slot, *pair_slot;
   uint64_t* el;
   double** slot_bc;
 };
@@ -526,51 +547,73 @@ static TablePtrs table_at(char* t, int B) {
   p.lane_own = p.lane_src + B;
   p.l0 = p.lane_own + B;
   p.lane_w = (double*)(p.l0 + B);
-  p.pa = (int8_t*)(p.lane_w + B);
+  p.pair = (int16_t*)(p.lane_w + B);
+  p.pa = (int8_t*)(p.pair + B);
   p.pb = p.pa + B;
   p.slot = p.pb + B;
-  p.el = (uint64_t*)(((uintptr_t)(p.slot + B) + 7) & ~(uintptr_t)7);
-  p.slot_bc = (double**)(p.el + 4);
+  p.pair_slot = p.slot + B;
+  p.el = (uint64_t*)(((uintptr_t)(p.pair_slot + kMaxPairs) + 7) & ~(uintptr_t)7);
+  p.slot_bc = (double**)(p.el + kMaxWords);
   return p;
 }
 
-// Fills one batch's table; returns the number of distinct source vertices.
-static int32_t fill_table(char* dst, const Packing& pk, int64_t b, const std::vector<Group>& groups, int B,
-                          double* const* slot_ptrs, int nslots) {
+struct TableInfo {
+  int32_t nl0;     // distinct source vertices
+  int32_t npairs;  // (word, slot) pairs
+  bool derived;    // any derived lane
+};
+
+// Fills one batch's table.  Pairs are numbered word by word in order of
+// first appearance; the per-pair sums of a launch are folded in that order.
+static TableInfo fill_table(char* dst, const Packing& pk, int64_t b, const std::vector<Group>& groups, int B,
+                            double* const* slot_ptrs, int nslots) {
   TablePtrs t = table_at(dst, B);
-  for (int k = 0; k < 4; ++k) t.el[k] = 0;
+  for (int k = 0; k < kMaxWords; ++k) t.el[k] = 0;
   for (int s = 0; s < kMaxSlots; ++s) t.slot_bc[s] = s < nslots ? slot_ptrs[s] : nullptr;
+  for (int p = 0; p < kMaxPairs; ++p) t.pair_slot[p] = 0;
+  TableInfo info{0, 0, false};
   std::vector<int32_t> distinct;
+  int cur_word = -1, cur_slot = -1;
   for (int j = 0; j < B; ++j) {
     const int32_t gi = pk.lane_group[(size_t)b * B + j];
     t.pa[j] = pk.pa[(size_t)b * B + j];
     t.pb[j] = pk.pb[(size_t)b * B + j];
     t.slot[j] = 0;
+    t.pair[j] = (int16_t)std::max(info.npairs - 1, 0);
     if (gi < 0) { t.lane_src[j] = -1; t.lane_own[j] = 0; t.lane_w[j] = 0.0; continue; }
     t.lane_src[j] = groups[gi].v;
     t.lane_own[j] = groups[gi].own;
     t.lane_w[j] = groups[gi].w;
     t.slot[j] = (int8_t)groups[gi].slot;
+    if ((j >> 6) != cur_word || groups[gi].slot != cur_slot) {
+      cur_word = j >> 6;
+      cur_slot = groups[gi].slot;
+      t.pair_slot[info.npairs] = (int8_t)cur_slot;
+      ++info.npairs;
+    }
+    t.pair[j] = (int16_t)(info.npairs - 1);
     distinct.push_back(groups[gi].v);
     if (t.pa[j] < 0) t.el[j >> 6] |= 1ull << (j & 63);
+    else info.derived = true;
   }
   std::sort(distinct.begin(), distinct.end());
   distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
   for (int j = 0; j < B; ++j) t.l0[j] = j < (int)distinct.size() ? distinct[j] : -1;
-  return (int32_t)distinct.size();
+  info.nl0 = (int32_t)distinct.size();
+  return info;
 }
 
 static void table_ptrs(char* dev, int B, BatchArgs* a) {
   TablePtrs t = table_at(dev, B);
   a->lane_src = t.lane_src;
   a->lane_own = t.lane_own;
-  a->l0 = t.l0;
   a->lane_w = t.lane_w;
   a->lane_pa = t.pa;
   a->lane_pb = t.pb;
-  a->lane_slot = t.slot;
   a->edge_lanes = t.el;
   a->slot_bc = t.slot_bc;
+  a->lane_pair = t.pair;
+  a->pair_slot = t.pair_slot;
 }
 
 struct CallOut {
@@ -616,10 +659,10 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
                       int cap_factor, hipStream_t st, double* const* slot_ptrs, int nslots, const TraceDev* tr,
                       CallOut* out, std::vector<int32_t>* trace_lane_vertex) {
   BatchWs w;
-  batch_layout(g->n, g->nnz, r.B, cap_factor, wsbase, &w);
+  batch_layout(g->n, g->nnz, r.B, cap_factor, r.max_slots, wsbase, &w);
   HIPCHK(hipMemsetAsync(w.ctl_begin, 0, w.ctl_bytes, st));
   HIPCHK(hipMemsetAsync(w.vis, 0, w.mask_bytes, st));
-  HIPCHK(hipMemsetAsync(w.stamp, 0xff, sizeof(int32_t) * (size_t)g->n, st));
+  HIPCHK(hipMemsetAsync(w.pair_bc, 0, sizeof(double) * (size_t)w.cap_pairs * g->n, st));
   Packing pk;
   pack_lanes(groups, triples, r.B, &pk);
   if (trace_lane_vertex) trace_lane_vertex->assign(pk.lane_group.begin(), pk.lane_group.end());
@@ -642,7 +685,6 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   a.se = w.se;
   a.vis = w.vis;
   a.fm = w.fm;
-  a.stamp = w.stamp;
   a.Q = w.Q;
   a.U = w.U;
   a.qoff = w.qoff;
@@ -651,7 +693,6 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   a.part_m = w.part_m;
   a.part_e = w.part_e;
   a.arrive = w.arrive;
-  a.gmulti = w.gmulti;
   a.err = w.err;
   a.lane_ovf = w.lane_ovf;
   a.ovf_list = w.ovf_list;
@@ -667,24 +708,25 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   a.cap_entries = (int32_t)w.caps.entries;
   a.cap_units = (int32_t)w.caps.units;
   a.cap_parts = (int32_t)w.caps.parts;
-  a.cap_multi = (int32_t)w.caps.multi;
   a.cap_levels = g->n + 3;
+  a.cap_pairs = w.cap_pairs;
+  a.pair_bc = w.pair_bc;
   bool any_own = false;
   for (const auto& gr : groups) any_own |= gr.own > 0;
   a.has_own = any_own ? 1 : 0;
   for (int64_t b0 = 0; b0 < pk.nbatches; b0 += kTableBatches) {
     const int64_t nb = std::min<int64_t>(kTableBatches, pk.nbatches - b0);
-    std::vector<int32_t> nl0(nb);
-    for (int64_t b = 0; b < nb; ++b)
-      nl0[b] = fill_table(stage + b * w.table_bytes, pk, b0 + b, groups, r.B, slot_ptrs, nslots);
+    std::vector<TableInfo> info(nb);
+    for (int64_t b = 0; b < nb; ++b) {
+      info[b] = fill_table(stage + b * w.table_bytes, pk, b0 + b, groups, r.B, slot_ptrs, nslots);
+      if (info[b].npairs > w.cap_pairs) return fail(BC_E_CAPACITY, "batch has more (word, slot) pairs than sized");
+    }
     HIPCHK(hipMemcpyAsync(w.tables, stage, nb * w.table_bytes, hipMemcpyHostToDevice, st));
     for (int64_t b = 0; b < nb; ++b) {
       char* t = w.tables + b * w.table_bytes;
       table_ptrs(t, r.B, &a);
-      a.nl0 = nl0[b];
-      bool hd = false;
-      for (int j = 0; j < r.B; ++j) hd |= pk.pa[(size_t)(b0 + b) * r.B + j] >= 0;
-      a.has_derived = hd ? 1 : 0;
+      a.npairs = info[b].npairs;
+      a.has_derived = info[b].derived ? 1 : 0;
       if (tr) {
         const size_t off = (size_t)b * r.B * g->n;
         a.delta_out = tr->delta ? tr->delta + off : nullptr;
@@ -831,7 +873,7 @@ static bc_status run_groups(bc_graph* g, const Resolved& r, bool ext, const Trav
   std::vector<Group> again = groups_at(g->n, groups, out->fail);
   Resolved r2 = r;
   while (r2.B > 64 && (int64_t)g->n * r2.B + 1024 > (int64_t)INT32_MAX / 2) {
-    r2.B /= 2;
+    r2.B = std::max(64, r2.B / 128 * 64);
     r2.K = r2.B / 64;
   }
   if ((int64_t)g->n * r2.B + 1024 > (int64_t)INT32_MAX / 2)
@@ -917,7 +959,9 @@ int64_t graph_n(const bc_graph* g) { return g->n; }
 int context_device(const bc_context* c) { return c->device; }
 int batch_occupancy(int K) {
   int e = 0, x = 0;
-  if (batch_max_grid(false, K, 256, &e) != hipSuccess || batch_max_grid(true, K, 256, &x) != hipSuccess) return 0;
+  (void)K;
+  if (batch_max_grid(false, kBatchBlock, &e) != hipSuccess || batch_max_grid(true, kBatchBlock, &x) != hipSuccess)
+    return 0;
   return std::min(e, x);
 }
 int64_t graph_nnz(const bc_graph* g) { return g->nnz; }
@@ -1027,11 +1071,11 @@ bc_status bc_autotune(bc_graph* g, const int32_t* sample, int64_t k, bc_compute_
     if (st == BC_OK && ms < best_ms) { best = o; best_ms = ms; }
     if (st != BC_OK && st != BC_E_CAPACITY) s = st;
   };
-  for (int B : {64, 128, 192, 256}) { bc_compute_opts o = best; o.batch = B; if (B != best.batch) consider(o); }
+  for (int B : {64, 128, 256, 512, 1024}) { bc_compute_opts o = best; o.batch = B; if (B != best.batch) consider(o); }
   for (double al : {-1.0, 0.5, 1.0, 2.0, 4.0, 8.0}) { bc_compute_opts o = best; o.alpha = al; consider(o); }
   {
     int occ = 0;
-    if (batch_max_grid(false, best.batch / 64, 256, &occ) == hipSuccess && occ > 1) {
+    if (batch_max_grid(false, kBatchBlock, &occ) == hipSuccess && occ > 1) {
       bc_compute_opts o = best;
       o.grid_per_cu = occ / 2;
       consider(o);
@@ -1108,7 +1152,7 @@ bc_status bc_trace(bc_graph* g, const int32_t* sources, int64_t k, const bc_comp
   // batched traces: every source its own lane, all in result slot 0 (scratch)
   const int B = r.B;
   BatchWs w;
-  batch_layout(n, g->nnz, B, B, ws, &w);
+  batch_layout(n, g->nnz, B, B, r.max_slots, ws, &w);
   const size_t cells = (size_t)B * n;
   double *dd = nullptr, *dbc = nullptr;
   uint64_t* dsg = nullptr;

@@ -19,6 +19,7 @@ struct Resolved {
   bool deg1, deg2;
   double alpha;
   int cap_factor = 32;  // batched level-list capacity: n * min(B, cap_factor) entries
+  int max_slots = 1;    // result slots one batch may feed (the server packs up to 64)
 };
 bc_status resolve_opts(const bc_graph* g, const bc_compute_opts* o, Resolved* r);
 void graph_groups(const bc_graph* g, const Resolved& r, const int32_t* sources, int64_t k, std::vector<Group>* groups,

@@ -1,44 +1,55 @@
 // Many sources per launch.  A batch of B = 64 K sources advances level by
-// level together inside one cooperative persistent kernel.  Lane j of a
+// level together inside one cooperative persistent kernel.  Lane j of the
 // 64-lane word k is source 64 k + j; per-(vertex, source) state is stored
 // source-minor ([vertex][lane]) so a wave touching one vertex reads or
 // writes one contiguous row per word.  Per vertex, 64-bit lane masks record
 // which sources have reached it (vis) and which sit on a given level (F_l,
 // four rotating arrays).
 //
-// Forward sweep (shortest-path counting, Alg. 2-3 generalised to B sources).
-// Phase k, one grid barrier each, does two independent jobs:
-//   counting of level k -- one wave per unit (<= 256 edges) of the level-k
-//     entries, lanes = sources: sigma(w) = sum of sigma(v) over neighbours v
-//     whose level-(k-1) mask has the lane's bit.  2-degree derived lanes
-//     (Lemma 1) take Eq. (6) instead: the sum of the two partner lanes'
-//     counts at w over the partners sitting on level k-1 at w.
-//   discovery of level k+1 -- top-down: one wave per unit of the level-k
-//     entries, lanes = edges; each edge ORs mask_k(v) & ~reached(w) into
-//     F_{k+1}(w); bottom-up: one wave per static unit of every vertex some
-//     source has not reached, OR-ing its neighbours' level-k masks.  A
-//     vertex entering level k+1 is appended once (per-level stamp).  Derived
-//     lanes are not propagated along edges: lane c reaches v at level k+1
-//     exactly when a partner sits on v at level k and c has not reached v.
-//   "reached(w)" is vis(w) | F_k(w): vis is being updated with F_k by the
-//   counting job of the same phase, and either value gives the same result.
+// Level lists hold (vertex, word) entries, cut into work units of <= 256
+// edges; every wave independently takes units.  An entry (v, k) joins level
+// l+1's list when the first lane of word k reaches v there: the atomic OR
+// that turns F_{l+1}(v, k) from zero to non-zero appends it.  Appends are
+// staged in the workgroup's LDS and flushed with one reservation per
+// workgroup and phase, so the level counters see a few hundred atomics per
+// level rather than one per discovering wave.
+//
+// Forward sweep (shortest-path counting, Alg. 2-3 generalised to B
+// sources).  Phase l, one grid barrier each, walks the level-l units once
+// and does two jobs per edge (w -> x):
+//   counting of level l -- sigma(w) gains sigma(x) on the lanes where x sits
+//     on level l-1 (rows gathered several at a time).  2-degree derived
+//     lanes (Lemma 1) take Eq. (6) instead: the sum of the two partner
+//     lanes' counts at w over the partners sitting on level l-1 at w.
+//   top-down discovery of level l+1 -- F_{l+1}(x) |= F_l(w) & ~reached(x),
+//     with reached(x) = vis(x) | F_l(x) (vis is being updated with F_l by
+//     the counting job of the same phase; either value gives the same
+//     result).  Bottom-up levels instead OR, for every (vertex, word) not
+//     yet reached by all the word's sources, its neighbours' level-l masks.
+//     Derived lanes are not propagated along edges: lane c reaches v at
+//     level l+1 exactly when a partner sits on v at level l and c has not
+//     reached v.
 // Backward sweep (dependency accumulation, Alg. 4-5, successor checking):
-//   one wave per unit of the level-l entries; per lane, sum psi over the
-//   neighbours whose level-(l+1) mask has the lane's bit, then
-//   delta = sigma * sum and psi = (1 + delta + omega) / sigma overwrite the
-//   count in place.  The vertex's score gains sum over its lanes of
-//   weight * (delta + omega), summed in lane order into each lane's result
-//   slot.
+//   per unit of the level-l entries, each lane sums psi over the neighbours
+//   whose level-(l+1) mask has the lane's bit, then delta = sigma * sum and
+//   psi = (1 + delta + omega) / sigma overwrite the count in place.  The
+//   lanes' weight * (delta + omega) are summed (lane order) per result slot
+//   into a per-(word, slot) array; after the sweep one pass folds those
+//   arrays into the slots' scores in word order.
 // Entries spanning several units combine per-unit partial sums in unit
-// order (the last arrival does it), so results do not depend on scheduling.
+// order (the last arriving wave does it), so results do not depend on
+// scheduling.
 #include "bc_common.h"
 #include "bc_kernels.h"
 
 namespace bcx {
 
 constexpr int CHB = kBatchChunk;
-constexpr int kGather = 8;  // neighbour rows loaded before any is consumed
-constexpr int kSlots = 4;   // rotating level-mask arrays
+constexpr int kSlots = 4;                          // rotating level-mask arrays
+constexpr int kStageCap = 2048;                    // staged appends per workgroup and phase
+constexpr int kWavesPB = kBatchBlock / kWave;
+constexpr int kStagePerThread = kStageCap / kBatchBlock;
+constexpr uint32_t kChunkMask = (1u << kUnitWordShift) - 1;
 
 __device__ __forceinline__ int32_t ldr32(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -53,377 +64,468 @@ __device__ __forceinline__ uint64_t rl64(uint64_t v, int src) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Stamp-protected append: a vertex joins level `lvl`'s list once.
-template <int CH>
-__device__ __forceinline__ void claim_and_append(const BatchArgs& a, const Lists& L, int lvl, int32_t ebase,
-                                                 int32_t ubase, bool want, int32_t w) {
-  bool claimed = false;
-  if (want && ldr32(&a.stamp[w]) != lvl) claimed = atomicExch(&a.stamp[w], lvl) != lvl;
-  append_entries<CH>(L, lvl, ebase, ubase, claimed, w);
-}
-
-// Per-wave run counters.
-template <int K>
-struct Counters {
-  uint64_t reached = 0, rnnz = 0, dag = 0, full = 0;
-  uint64_t ns[K];
+// Workgroup-shared state.
+struct Stage {
+  uint64_t e[kStageCap];  // staged entries of the level being discovered
+  int32_t n;              // entries staged (may pass kStageCap: the rest went straight to the list)
+  int32_t base_e, base_u, base_p;
+  unsigned long long full;
+  uint64_t wu[kWavesPB], wp[kWavesPB], wd[kWavesPB];
+  uint64_t sX[kMaxWords];
+  unsigned long long ctr[3];
 };
 
-// ------------------------------------------------------------ counting
+__device__ __forceinline__ void raise_b(const BatchArgs& a, int lvl, int32_t code) {
+  atomicOr(&a.lc[lvl].err, code);
+  atomicOr(a.err, code);
+}
 
-// Counts of the new lanes of one level-k unit.  `par` = level-(k-1) masks,
-// `now` = level-k masks.
-template <bool EXT, int K>
-__device__ __forceinline__ void count_unit(const BatchArgs& a, const Unit& un, const uint64_t* par,
-                                           const uint64_t* now, int k_level, const uint64_t (&EL)[K],
-                                           Counters<K>& C) {
-  constexpr int B = 64 * K;
+// Writes entry `ent` at list position e with its units at u (partial-sum
+// slots at pb when it spans several units).
+__device__ __forceinline__ void write_entry(const BatchArgs& a, int lvl, int64_t e, int64_t u, int64_t pb,
+                                            uint64_t ent, int32_t nun) {
+  const int32_t v = (int32_t)(uint32_t)ent;
+  const int32_t kw = (int32_t)(ent >> 32) << kUnitWordShift;
+  if (e >= a.cap_entries) {
+    raise_b(a, lvl, kErrCapEntries);
+  } else if (u + nun > a.cap_units) {
+    raise_b(a, lvl, kErrCapUnits);
+  } else if (nun > 1 && pb + nun > a.cap_parts) {
+    raise_b(a, lvl, kErrCapPartials);
+  } else {
+    a.Q[e] = ent;
+    if (nun == 1) {
+      a.U[u] = Unit{v, kw, -1, 0};
+    } else {
+      a.arrive[e] = 0;
+      for (int32_t c = 0; c < nun; ++c) a.U[u + c] = Unit{v, kw | c, (int32_t)e, (int32_t)pb};
+    }
+  }
+}
+
+// Direct append of one wave's lanes (staging buffer full).
+__device__ __forceinline__ void global_append(const BatchArgs& a, int lvl, int32_t ebase, int32_t ubase, bool want,
+                                           uint64_t ent) {
+  if (ballot(want) == 0) return;
+  int32_t deg = 0, nun = 0;
+  if (want) {
+    const int32_t v = (int32_t)(uint32_t)ent;
+    deg = a.rp[v + 1] - a.rp[v];
+    nun = units_of<CHB>(deg);
+  }
+  const uint64_t contrib = want ? ((1ull << 32) | (uint64_t)(uint32_t)nun) : 0ull;
+  const uint64_t incl = wave_incl_scan_u64(contrib);
+  const uint64_t total = shfl(incl, kWave - 1);
+  const uint64_t dsum = wave_sum_u64(want ? (uint64_t)deg : 0ull);
+  unsigned long long base = 0;
+  if (lane_id() == kWave - 1) {
+    base = atomicAdd(&a.lc[lvl].packed, (unsigned long long)total);
+    atomicAdd(&a.lc[lvl].fedges, (unsigned long long)dsum);
+  }
+  base = shfl((uint64_t)base, kWave - 1);
+  if (want) {
+    const uint64_t my = base + incl - contrib;
+    int64_t pb = 0;
+    if (nun > 1) pb = atomicAdd(&a.lc[lvl].pslots, nun);
+    write_entry(a, lvl, (int64_t)ebase + (int64_t)(my >> 32), (int64_t)ubase + (int64_t)(my & 0xffffffffull), pb,
+                ent, nun);
+  }
+}
+
+// Appends the lanes with `want` (one wave, all lanes calling).
+__device__ __forceinline__ void stage_append(const BatchArgs& a, Stage& st, int lvl, int32_t ebase, int32_t ubase,
+                                             bool want, uint64_t ent) {
+  const uint64_t wm = ballot(want);
+  if (wm == 0) return;
+  int pos = 0;
+  if (lane_id() == 0) pos = atomicAdd(&st.n, __popcll(wm));
+  pos = __shfl(pos, 0, kWave);
+  const int r = pos + lanes_below(wm);
+  const bool in = want && r < kStageCap;
+  if (in) st.e[r] = ent;
+  if (pos + __popcll(wm) > kStageCap) global_append(a, lvl, ebase, ubase, want && !in, ent);
+}
+
+// Flushes the staged entries of level `lvl` (whole workgroup): one
+// reservation of entries, units, partial-sum slots and frontier edges.
+__device__ __forceinline__ void stage_flush(const BatchArgs& a, Stage& st, int lvl, int32_t ebase, int32_t ubase) {
+  __syncthreads();
+  const int cnt = min(st.n, kStageCap);
+  const int t = (int)threadIdx.x, lane = lane_id(), wv = t >> 6;
+  if (cnt > 0) {
+    int32_t nun[kStagePerThread];
+    uint64_t su = 0, sp = 0, sd = 0;
+#pragma unroll 1
+    for (int r = 0; r < kStagePerThread; ++r) {
+      const int i = t * kStagePerThread + r;
+      nun[r] = 0;
+      if (i < cnt) {
+        const int32_t v = (int32_t)(uint32_t)st.e[i];
+        const int32_t deg = a.rp[v + 1] - a.rp[v];
+        nun[r] = units_of<CHB>(deg);
+        su += (uint64_t)nun[r];
+        sd += (uint64_t)deg;
+        if (nun[r] > 1) sp += (uint64_t)nun[r];
+      }
+    }
+    const uint64_t iu = wave_incl_scan_u64(su), ip = wave_incl_scan_u64(sp);
+    const uint64_t ds = wave_sum_u64(sd);
+    if (lane == kWave - 1) { st.wu[wv] = iu; st.wp[wv] = ip; st.wd[wv] = ds; }
+    __syncthreads();
+    if (t == 0) {
+      uint64_t tu = 0, tp = 0, td = 0;
+      for (int w = 0; w < kWavesPB; ++w) {
+        const uint64_t u = st.wu[w], p = st.wp[w];
+        st.wu[w] = tu;
+        st.wp[w] = tp;
+        tu += u;
+        tp += p;
+        td += st.wd[w];
+      }
+      const unsigned long long b =
+          atomicAdd(&a.lc[lvl].packed, ((unsigned long long)cnt << 32) | (unsigned long long)tu);
+      if (td) atomicAdd(&a.lc[lvl].fedges, (unsigned long long)td);
+      st.base_e = (int32_t)(b >> 32);
+      st.base_u = (int32_t)(b & 0xffffffffull);
+      st.base_p = tp ? atomicAdd(&a.lc[lvl].pslots, (int32_t)tp) : 0;
+    }
+    __syncthreads();
+    int64_t uo = (int64_t)ubase + st.base_u + (int64_t)(st.wu[wv] + iu - su);
+    int64_t po = (int64_t)st.base_p + (int64_t)(st.wp[wv] + ip - sp);
+#pragma unroll 1
+    for (int r = 0; r < kStagePerThread; ++r) {
+      const int i = t * kStagePerThread + r;
+      if (i < cnt) {
+        write_entry(a, lvl, (int64_t)ebase + st.base_e + i, uo, po, st.e[i], nun[r]);
+        uo += nun[r];
+        if (nun[r] > 1) po += nun[r];
+      }
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    st.n = 0;
+    if (st.full) atomicAdd(a.fulledges, st.full);
+    st.full = 0;
+  }
+}
+
+// Per-wave run counters (dag per lane, the others uniform).
+struct Ctr {
+  uint64_t reached = 0, rnnz = 0, dag = 0, full = 0;
+};
+
+// ------------------------------------------------------------ forward unit
+
+// A unit of level kl: counting of level kl (when `count`) and top-down
+// discovery of level kl+1 (when `td`).
+template <bool EXT>
+__device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, const Unit& un, const uint64_t* par,
+                                             const uint64_t* cur, uint64_t* nxt, int kl, bool count, bool td,
+                                             int32_t ebn, int32_t ubn, Ctr& C) {
+  constexpr int G = EXT ? 8 : 16;  // neighbour rows loaded before any is consumed
+  const int K = a.K;
+  const size_t B = (size_t)64 * K;
   const int lane = lane_id();
   const int32_t* __restrict__ rp = a.rp;
   const int32_t* __restrict__ ci = a.ci;
   const int32_t w = un.v;
+  const int k = (int)((uint32_t)un.c >> kUnitWordShift);
+  const int32_t c = (int32_t)((uint32_t)un.c & kChunkMask);
   const int32_t rb = rp[w], re = rp[w + 1];
-  const int32_t beg = rb + un.c * CHB;
-  const int32_t end = min(re, beg + CHB);
-  uint64_t nbm[K], em[K];
-  bool anye = false;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    nbm[k] = now[(size_t)w * K + k];
-    em[k] = nbm[k] & EL[k];
-    anye |= em[k] != 0;
-  }
-  uint64_t s[K];
-  Ext x[K];
-  bool wrap[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) { s[k] = 0; x[k] = ext_zero(); wrap[k] = false; }
-  if (anye) {
+  const size_t wk = (size_t)w * K + k;
+  const uint64_t EL = a.edge_lanes[k];
+  const uint64_t nbm = cur[wk];  // lanes of word k on level kl at w
+  const uint64_t em = nbm & EL;  // of them, lanes that count and propagate along edges
+  const bool cnt = count && em != 0;
+  const bool disc = td && em != 0;
+  uint64_t s = 0;
+  Ext x = ext_zero();
+  bool wrap = false;
+  if (cnt || disc) {
+    const int32_t beg = rb + c * CHB;
+    const int32_t end = min(re, beg + CHB);
     for (int32_t off0 = beg; off0 < end; off0 += kWave) {
       const int32_t off = off0 + lane;
       int32_t vl = 0;
-      uint64_t ml[K];
+      uint64_t ml = 0;
+      bool claimed = false;
       if (off < end) {
         vl = ci[off];
-#pragma unroll
-        for (int k = 0; k < K; ++k) ml[k] = par[(size_t)vl * K + k] & em[k];
-      } else {
-#pragma unroll
-        for (int k = 0; k < K; ++k) ml[k] = 0;
+        const size_t xk = (size_t)vl * K + k;
+        if (cnt) ml = par[xk] & em;
+        if (disc) {
+          const uint64_t nb = em & ~(a.vis[xk] | cur[xk]);
+          if (nb) claimed = atomicOr((unsigned long long*)&nxt[xk], (unsigned long long)nb) == 0ull;
+        }
       }
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        C.dag += (uint64_t)__popcll(ml[k]);
-        // only the neighbours with a wanted lane; 8 rows in flight per word
-        uint64_t act = ballot(ml[k] != 0);
+      if (cnt) {
+        C.dag += (uint64_t)__popcll(ml);
+        uint64_t act = ballot(ml != 0);
         while (act) {
-          int ti[kGather];
+          int ti[G];
 #pragma unroll
-          for (int i = 0; i < kGather; ++i) {
+          for (int i = 0; i < G; ++i) {
             ti[i] = act ? __builtin_ctzll(act) : -1;
             act &= act ? act - 1 : 0ull;
           }
           if (EXT) {
-            Ext xs[kGather];
+            Ext xs[G];
 #pragma unroll
-            for (int i = 0; i < kGather; ++i) {
+            for (int i = 0; i < G; ++i) {
               xs[i] = ext_zero();
               if (ti[i] >= 0) {
                 const int32_t v = rl32(vl, ti[i]);
-                const uint64_t mv = rl64(ml[k], ti[i]);
-                const size_t row = (size_t)v * B + 64 * k;  // uniform: scalar base + lane offset
+                const uint64_t mv = rl64(ml, ti[i]);
+                const size_t row = (size_t)v * B + 64 * k;  // uniform base, lane offset
                 if ((mv >> lane) & 1ull) xs[i] = Ext{(a.sm + row)[lane], (a.se + row)[lane]};
               }
             }
 #pragma unroll
-            for (int i = 0; i < kGather; ++i) x[k] = ext_add(x[k], xs[i]);
+            for (int i = 0; i < G; ++i) x = ext_add(x, xs[i]);
           } else {
-            uint64_t ys[kGather];
+            uint64_t ys[G];
 #pragma unroll
-            for (int i = 0; i < kGather; ++i) {
+            for (int i = 0; i < G; ++i) {
               ys[i] = 0;
               if (ti[i] >= 0) {
                 const int32_t v = rl32(vl, ti[i]);
-                const uint64_t mv = rl64(ml[k], ti[i]);
+                const uint64_t mv = rl64(ml, ti[i]);
                 const uint64_t* row = a.sig + (size_t)v * B + 64 * k;  // uniform base, lane offset
                 if ((mv >> lane) & 1ull) ys[i] = row[lane];
               }
             }
 #pragma unroll
-            for (int i = 0; i < kGather; ++i) {
-              if (s[k] + ys[i] < s[k]) wrap[k] = true;
-              s[k] += ys[i];
+            for (int i = 0; i < G; ++i) {
+              if (s + ys[i] < s) wrap = true;
+              s += ys[i];
             }
           }
         }
       }
+      if (disc) stage_append(a, st, kl + 1, ebn, ubn, claimed, bentry(vl, k));
     }
   }
-  // combine the units of a split entry in unit order
+  if (!count) return;
+  // combine the units of a split entry in unit order (the last arriving wave)
   if (un.mi >= 0) {
     const int32_t nunits = units_of<CHB>(re - rb);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const size_t pi = ((size_t)(un.pb + un.c) * K + k) * 64 + lane;
-      if (EXT) { a.part_m[pi] = x[k].m; a.part_e[pi] = x[k].e; }
-      else { a.part_m[pi] = __longlong_as_double((long long)s[k]); a.part_e[pi] = wrap[k] ? 1 : 0; }
-    }
+    const size_t pi = (size_t)(un.pb + c) * 64 + lane;
+    if (EXT) { a.part_m[pi] = x.m; a.part_e[pi] = x.e; }
+    else { a.part_m[pi] = __longlong_as_double((long long)s); a.part_e[pi] = wrap ? 1 : 0; }
     fence_release();
     int32_t prev = 0;
     if (lane == 0) prev = atomicAdd(&a.arrive[un.mi], 1);
     prev = __shfl(prev, 0, kWave);
     if (prev != nunits - 1) return;
     fence_acquire();
-#pragma unroll
-    for (int k = 0; k < K; ++k) { s[k] = 0; x[k] = ext_zero(); wrap[k] = false; }
-    for (int32_t c = 0; c < nunits; ++c) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const size_t pi = ((size_t)(un.pb + c) * K + k) * 64 + lane;
-        const double pm = __hip_atomic_load(&a.part_m[pi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int32_t pe = __hip_atomic_load(&a.part_e[pi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (EXT) {
-          x[k] = ext_add(x[k], Ext{pm, pe});
-        } else {
-          const uint64_t y = (uint64_t)__double_as_longlong(pm);
-          if (s[k] + y < s[k] || pe) wrap[k] = true;
-          s[k] += y;
-        }
-      }
-    }
-  }
-  // finalise: counts, levels, visited masks; derived lanes by Eq. (6)
-  const uint64_t* parw = par + (size_t)w * K;
-  bool fullnow = true;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const size_t idx = (size_t)w * B + 64 * k + lane;
-    if ((nbm[k] >> lane) & 1ull) {
-      if (!((em[k] >> lane) & 1ull)) {
-        const int pa = a.lane_pa[64 * k + lane], pb = a.lane_pb[64 * k + lane];
-        const uint64_t cw = parw[k];
-        const size_t ia = (size_t)w * B + 64 * k + pa, ib = (size_t)w * B + 64 * k + pb;
-        if (EXT) {
-          Ext t = ext_zero();
-          if ((cw >> pa) & 1ull) t = ext_add(t, Ext{a.sm[ia], a.se[ia]});
-          if ((cw >> pb) & 1ull) t = ext_add(t, Ext{a.sm[ib], a.se[ib]});
-          x[k] = t;
-        } else {
-          uint64_t t = 0;
-          if ((cw >> pa) & 1ull) t += a.sig[ia];
-          if ((cw >> pb) & 1ull) {
-            const uint64_t y = a.sig[ib];
-            if (t + y < t) wrap[k] = true;
-            t += y;
-          }
-          s[k] = t;
-        }
-      }
+    s = 0;
+    x = ext_zero();
+    wrap = false;
+    for (int32_t cc = 0; cc < nunits; ++cc) {
+      const size_t pc = (size_t)(un.pb + cc) * 64 + lane;
+      const double pm = __hip_atomic_load(&a.part_m[pc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int32_t pe = __hip_atomic_load(&a.part_e[pc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (EXT) {
-        const Ext z = ext_norm(x[k]);
-        a.sm[idx] = z.m;
-        a.se[idx] = z.e;
+        x = ext_add(x, Ext{pm, pe});
       } else {
-        a.sig[idx] = s[k];
-        if (wrap[k]) atomicOr(&a.lane_ovf[64 * k + lane], 1u);
+        const uint64_t y = (uint64_t)__double_as_longlong(pm);
+        if (s + y < s || pe) wrap = true;
+        s += y;
       }
-      a.lv[idx] = k_level;
-      if (a.has_own) C.ns[k] += 1 + (a.omega ? (uint64_t)a.omega[w] : 0);
-    }
-    const uint64_t nv = a.vis[(size_t)w * K + k] | nbm[k];
-    if (lane == 0) a.vis[(size_t)w * K + k] = nv;
-    fullnow &= (nv & EL[k]) == EL[k];
-    if (lane == 0) {
-      const uint64_t pc = (uint64_t)__popcll(nbm[k]);
-      C.reached += pc;
-      C.rnnz += pc * (uint64_t)(re - rb);
     }
   }
-  if (fullnow && lane == 0) C.full += (uint64_t)(re - rb);
+  // finalise word k at w: counts, levels, visited mask; derived lanes by Eq. (6)
+  if ((nbm >> lane) & 1ull) {
+    const size_t idx = (size_t)w * B + 64 * k + lane;
+    if (!((em >> lane) & 1ull)) {
+      const int pa = a.lane_pa[64 * k + lane], pb = a.lane_pb[64 * k + lane];
+      const uint64_t cw = par[wk];
+      const size_t ia = (size_t)w * B + 64 * k + pa, ib = (size_t)w * B + 64 * k + pb;
+      if (EXT) {
+        Ext t = ext_zero();
+        if ((cw >> pa) & 1ull) t = ext_add(t, Ext{a.sm[ia], a.se[ia]});
+        if ((cw >> pb) & 1ull) t = ext_add(t, Ext{a.sm[ib], a.se[ib]});
+        x = t;
+      } else {
+        uint64_t t = 0;
+        if ((cw >> pa) & 1ull) t += a.sig[ia];
+        if ((cw >> pb) & 1ull) {
+          const uint64_t y = a.sig[ib];
+          if (t + y < t) wrap = true;
+          t += y;
+        }
+        s = t;
+      }
+    }
+    if (EXT) {
+      const Ext z = ext_norm(x);
+      a.sm[idx] = z.m;
+      a.se[idx] = z.e;
+    } else {
+      a.sig[idx] = s;
+      if (wrap) atomicOr(&a.lane_ovf[64 * k + lane], 1u);
+    }
+    a.lv[idx] = kl;
+  }
+  if (lane == 0) {
+    const uint64_t ov = a.vis[wk];
+    const uint64_t nv = ov | nbm;
+    a.vis[wk] = nv;
+    // edges of word k no source of the word can still discover
+    if ((nv & EL) == EL && (ov & EL) != EL) C.full += (uint64_t)(re - rb);
+  }
+  const uint64_t pc = (uint64_t)__popcll(nbm);
+  C.reached += pc;
+  C.rnnz += pc * (uint64_t)(re - rb);
 }
 
-// ----------------------------------------------------------- backward
+// ----------------------------------------------------------- backward unit
 
-template <bool EXT, int K>
+template <bool EXT>
 __device__ __forceinline__ void backward_unit(const BatchArgs& a, const Unit& un, const uint64_t* cmv, uint64_t* own,
-                                              int lb, int depth, const uint64_t (&X)[K]) {
-  constexpr int B = 64 * K;
+                                              int lb, int depth, const Stage& st) {
+  constexpr int G = EXT ? 8 : 16;
+  const int K = a.K;
+  const size_t B = (size_t)64 * K;
   const int lane = lane_id();
   const int32_t* __restrict__ rp = a.rp;
   const int32_t* __restrict__ ci = a.ci;
   double* psi = EXT ? a.sm : (double*)a.sig;
   const int32_t w = un.v;
+  const int k = (int)((uint32_t)un.c >> kUnitWordShift);
+  const int32_t c = (int32_t)((uint32_t)un.c & kChunkMask);
   const int32_t rb = rp[w], re = rp[w + 1];
-  uint64_t om[K];
-  bool anyo = false;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const size_t idx = (size_t)w * B + 64 * k + lane;
-    const bool r = (a.vis[(size_t)w * K + k] >> lane) & 1ull;
-    om[k] = ballot(r && a.lv[idx] == lb) & ~X[k];
-    anyo |= om[k] != 0;
-    if (un.c == 0 && lane == 0) own[(size_t)w * K + k] = om[k];
-  }
-  double acc[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  int32_t ew[K];
-  if (EXT) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) ew[k] = ((om[k] >> lane) & 1ull) ? a.se[(size_t)w * B + 64 * k + lane] : 0;
-  }
-  if (anyo && lb < depth) {
-    const int32_t beg = rb + un.c * CHB;
+  const size_t wk = (size_t)w * K + k;
+  const size_t idx = (size_t)w * B + 64 * k + lane;
+  const bool r = (a.vis[wk] >> lane) & 1ull;
+  const uint64_t om = ballot(r && a.lv[idx] == lb) & ~st.sX[k];
+  if (c == 0 && lane == 0) own[wk] = om;
+  double acc = 0.0;
+  if (om && lb < depth) {
+    const int32_t ew = (EXT && ((om >> lane) & 1ull)) ? a.se[idx] : 0;
+    const int32_t beg = rb + c * CHB;
     const int32_t end = min(re, beg + CHB);
     for (int32_t off0 = beg; off0 < end; off0 += kWave) {
       const int32_t off = off0 + lane;
       int32_t vl = 0;
-      uint64_t ml[K];
+      uint64_t ml = 0;
       if (off < end) {
         vl = ci[off];
-#pragma unroll
-        for (int k = 0; k < K; ++k) ml[k] = cmv[(size_t)vl * K + k] & om[k];
-      } else {
-#pragma unroll
-        for (int k = 0; k < K; ++k) ml[k] = 0;
+        ml = cmv[(size_t)vl * K + k] & om;
       }
+      uint64_t act = ballot(ml != 0);
+      while (act) {
+        int ti[G];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        uint64_t act = ballot(ml[k] != 0);
-        while (act) {
-          int ti[kGather];
+        for (int i = 0; i < G; ++i) {
+          ti[i] = act ? __builtin_ctzll(act) : -1;
+          act &= act ? act - 1 : 0ull;
+        }
+        double ys[G];
 #pragma unroll
-          for (int i = 0; i < kGather; ++i) {
-            ti[i] = act ? __builtin_ctzll(act) : -1;
-            act &= act ? act - 1 : 0ull;
-          }
-          double ys[kGather];
-#pragma unroll
-          for (int i = 0; i < kGather; ++i) {
-            ys[i] = 0.0;
-            if (ti[i] >= 0) {
-              const int32_t v = rl32(vl, ti[i]);
-              const uint64_t mv = rl64(ml[k], ti[i]);
-              const size_t row = (size_t)v * B + 64 * k;  // uniform base, lane offset
-              if ((mv >> lane) & 1ull) {
-                ys[i] = (psi + row)[lane];
-                if (EXT) ys[i] = ldexp(ys[i], ew[k] - (a.se + row)[lane]);
-              }
+        for (int i = 0; i < G; ++i) {
+          ys[i] = 0.0;
+          if (ti[i] >= 0) {
+            const int32_t v = rl32(vl, ti[i]);
+            const uint64_t mv = rl64(ml, ti[i]);
+            const size_t row = (size_t)v * B + 64 * k;  // uniform base, lane offset
+            if ((mv >> lane) & 1ull) {
+              ys[i] = (psi + row)[lane];
+              if (EXT) ys[i] = ldexp(ys[i], ew - (a.se + row)[lane]);
             }
           }
-#pragma unroll
-          for (int i = 0; i < kGather; ++i) acc[k] += ys[i];
         }
+#pragma unroll
+        for (int i = 0; i < G; ++i) acc += ys[i];
       }
     }
   }
   if (un.mi >= 0) {
     const int32_t nunits = units_of<CHB>(re - rb);
-#pragma unroll
-    for (int k = 0; k < K; ++k) a.part_m[((size_t)(un.pb + un.c) * K + k) * 64 + lane] = acc[k];
+    a.part_m[(size_t)(un.pb + c) * 64 + lane] = acc;
     fence_release();
     int32_t prev = 0;
     if (lane == 0) prev = atomicAdd(&a.arrive[un.mi], 1);
     prev = __shfl(prev, 0, kWave);
     if (prev != 2 * nunits - 1) return;  // the forward counting phase took the first nunits arrivals
     fence_acquire();
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = 0.0;
-    for (int32_t c = 0; c < nunits; ++c) {
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-        acc[k] += __hip_atomic_load(&a.part_m[((size_t)(un.pb + c) * K + k) * 64 + lane], __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
-    }
+    acc = 0.0;
+    for (int32_t cc = 0; cc < nunits; ++cc)
+      acc += __hip_atomic_load(&a.part_m[(size_t)(un.pb + cc) * 64 + lane], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (!anyo) return;
+  if (!om) return;
   const double omw = a.omega ? (double)a.omega[w] : 0.0;
-  // contributions go to each lane's result slot; lanes of one slot are
-  // summed in lane order, words in order, slots in order of first lane
-  double cs[K];
-  int sl[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    cs[k] = 0.0;
-    sl[k] = a.lane_slot[64 * k + lane];
-    if ((om[k] >> lane) & 1ull) {
-      const size_t idx = (size_t)w * B + 64 * k + lane;
-      const double sw = EXT ? a.sm[idx] : (double)a.sig[idx];
-      const double delta = sw * acc[k];
-      psi[idx] = (1.0 + delta + omw) / sw;
-      cs[k] = a.lane_w[64 * k + lane] * (delta + omw);
-      if (a.delta_out) a.delta_out[(size_t)(64 * k + lane) * a.n + w] = delta;
-    }
+  double cs = 0.0;
+  if ((om >> lane) & 1ull) {
+    const double sw = EXT ? a.sm[idx] : (double)a.sig[idx];
+    const double delta = sw * acc;
+    psi[idx] = (1.0 + delta + omw) / sw;
+    cs = a.lane_w[64 * k + lane] * (delta + omw);
+    if (a.delta_out) a.delta_out[(size_t)(64 * k + lane) * a.n + w] = delta;
   }
-  int slot = -1;
-  double tot = 0.0;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    uint64_t rem = om[k];
-    while (rem) {
-      const int first = __builtin_ctzll(rem);
-      const int sv = __builtin_amdgcn_readlane(sl[k], first);
-      const uint64_t same = ballot(sl[k] == sv) & rem;
-      const double part = wave_sum(((same >> lane) & 1ull) ? cs[k] : 0.0);
-      if (sv != slot) {
-        if (slot >= 0 && lane == 0) a.slot_bc[slot][w] += tot;
-        slot = sv;
-        tot = 0.0;
-      }
-      tot += part;
-      rem &= ~same;
-    }
+  // per (word, slot) sums in lane order
+  const int pr = a.lane_pair[64 * k + lane];
+  uint64_t rem = om;
+  while (rem) {
+    const int pv = __builtin_amdgcn_readlane(pr, __builtin_ctzll(rem));
+    const uint64_t same = ballot(pr == pv) & rem;
+    const double part = wave_sum(((same >> lane) & 1ull) ? cs : 0.0);
+    if (lane == 0) a.pair_bc[(size_t)pv * a.n + w] += part;
+    rem &= ~same;
   }
-  if (slot >= 0 && lane == 0) a.slot_bc[slot][w] += tot;
 }
 
 // ------------------------------------------------------------- kernel
 
-template <bool EXT, int K>
-__global__ void __launch_bounds__(256) batch_kernel(BatchArgs a) {
-  constexpr int B = 64 * K;
+template <bool EXT>
+__global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_eu(4))) batch_kernel(BatchArgs a) {
+  __shared__ Stage st;
+  const int K = a.K;
+  const size_t B = (size_t)64 * K;
   const int lane = lane_id();
-  const int wpb = blockDim.x / kWave;
-  const int gw = blockIdx.x * wpb + (int)(threadIdx.x / kWave);
-  const int nw = gridDim.x * wpb;
+  const int wib = (int)(threadIdx.x >> 6);
+  const int64_t gw = (int64_t)blockIdx.x * kWavesPB + wib;
+  const int64_t nw = (int64_t)gridDim.x * kWavesPB;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
   const int32_t n = a.n;
   const int32_t* __restrict__ rp = a.rp;
   const int32_t* __restrict__ ci = a.ci;
-  const Lists L{a.Q, a.U, a.lc, a.arrive, a.gmulti, a.err, a.rp,
-                a.cap_entries, a.cap_units, a.cap_parts, a.cap_multi};
-  uint64_t EL[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) EL[k] = a.edge_lanes[k];
   const size_t fms = (size_t)n * K;
   auto F = [&](int level) { return a.fm + (size_t)(level % kSlots) * fms; };
-  Counters<K> C;
-#pragma unroll
-  for (int k = 0; k < K; ++k) C.ns[k] = 0;
-
-  // ---- seed the sources at level 0 (masks and stamps are clear on entry)
-  for (int64_t j = tid; j < B; j += nth) {
-    const int32_t s = a.lane_src[j];
-    if (s >= 0) {
-      const uint64_t bit = 1ull << (j & 63);
-      a.lv[(size_t)s * B + j] = 0;
-      if (EXT) { a.sm[(size_t)s * B + j] = 1.0; a.se[(size_t)s * B + j] = 0; }
-      else a.sig[(size_t)s * B + j] = 1ull;
-      atomicOr((unsigned long long*)&a.vis[(size_t)s * K + (j >> 6)], (unsigned long long)bit);
-      atomicOr((unsigned long long*)&a.fm[(size_t)s * K + (j >> 6)], (unsigned long long)bit);
-      a.lane_ns[j] = 1 + (a.omega ? (uint64_t)a.omega[s] : 0);
-      C.reached += 1;
-      C.rnnz += (uint64_t)(rp[s + 1] - rp[s]);
-    }
+  int kact = 0;  // words with lanes that propagate along edges
+  for (int k = 0; k < K; ++k) kact += a.edge_lanes[k] != 0;
+  Ctr C;
+  if (threadIdx.x == 0) {
+    st.n = 0;
+    st.full = 0;
+    st.ctr[0] = st.ctr[1] = st.ctr[2] = 0;
   }
-  if (gw == 0) {
-    for (int32_t base = 0; base < a.nl0; base += kWave) {
-      const bool want = base + lane < a.nl0;
-      const int32_t s = want ? a.l0[base + lane] : 0;
-      if (want) a.stamp[s] = 0;
-      append_entries<CHB>(L, 0, 0, 0, want, s);
+  __syncthreads();
+
+  // ---- seed the sources at level 0 (masks are clear on entry)
+  {
+    bool claimed = false;
+    uint64_t ent = 0;
+    if (tid < (int64_t)B) {
+      const int32_t s = a.lane_src[tid];
+      if (s >= 0) {
+        const int j = (int)tid;
+        const uint64_t bit = 1ull << (j & 63);
+        a.lv[(size_t)s * B + j] = 0;
+        if (EXT) { a.sm[(size_t)s * B + j] = 1.0; a.se[(size_t)s * B + j] = 0; }
+        else a.sig[(size_t)s * B + j] = 1ull;
+        atomicOr((unsigned long long*)&a.vis[(size_t)s * K + (j >> 6)], (unsigned long long)bit);
+        claimed = atomicOr((unsigned long long*)&a.fm[(size_t)s * K + (j >> 6)], (unsigned long long)bit) == 0ull;
+        ent = bentry(s, j >> 6);
+        atomicAdd(&st.ctr[0], 1ull);
+        atomicAdd(&st.ctr[1], (unsigned long long)(rp[s + 1] - rp[s]));
+      }
     }
+    stage_append(a, st, 0, 0, 0, claimed, ent);
+    stage_flush(a, st, 0, 0, 0);
   }
   if (tid == 0) { a.qoff[0] = 0; a.uoff[0] = 0; }
   grid_barrier(a.bar);
@@ -445,118 +547,72 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchArgs a) {
     const uint64_t* cur = F(kl);
     uint64_t* nxt = F(nl);
     uint64_t* clr = F(kl + 2);                 // level kl-2
-    const uint64_t fe = ldr64(&a.lc[kl].fedges);
-    const uint64_t full = ldr64(a.fulledges);
-    const double unvisited = (double)a.nnz - (double)full;
-    const bool bu = kl > 0 && a.alpha > 0.0 && (double)fe * a.alpha > unvisited;
+    // direction: bottom-up once the frontier's edges outweigh alpha times
+    // the edges still undiscovered (both counted once per word)
+    const double fe = (double)ldr64(&a.lc[kl].fedges);
+    const double unvisited = (double)a.nnz * kact - (double)ldr64(a.fulledges);
+    const bool bu = kl > 0 && a.alpha > 0.0 && fe * a.alpha > unvisited;
     if (tid == 0) {
       a.qoff[nl] = ebn;
       a.uoff[nl] = ubn;
       if (kl + 2 < a.cap_levels) a.lc[kl + 2] = LevelCtr{0ull, 0, 0, 0ull, 0, 0};
     }
     ++levels;
-    // counting of level kl
-    if (kl >= 1) {
-      for (int32_t u = ubase + gw; u < ubn; u += nw) count_unit<EXT, K>(a, a.U[u], par, cur, kl, EL, C);
+    if (kl >= 1 || !bu) {
+      for (int64_t i = gw; i < nu; i += nw)
+        forward_unit<EXT>(a, st, a.U[ubase + i], par, cur, nxt, kl, kl >= 1, !bu, ebn, ubn, C);
     }
-    // discovery of level kl+1
-    if (!bu) {
-      for (int32_t u = ubase + gw; u < ubn; u += nw) {
-        const Unit un = a.U[u];
-        const int32_t v = un.v;
-        uint64_t cm[K];
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < K; ++k) { cm[k] = cur[(size_t)v * K + k] & EL[k]; any |= cm[k] != 0; }
-        if (!any) continue;  // only derived lanes on v (uniform)
-        const int32_t beg = rp[v] + un.c * CHB;
-        const int32_t end = min(rp[v + 1], beg + CHB);
-        for (int32_t off0 = beg; off0 < end; off0 += kWave) {
-          const int32_t off = off0 + lane;
-          bool want = false;
-          int32_t w = 0;
-          if (off < end) {
-            w = ci[off];
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-              const uint64_t reached = a.vis[(size_t)w * K + k] | cur[(size_t)w * K + k];
-              const uint64_t nb = cm[k] & ~reached;
-              if (nb) {
-                atomicOr((unsigned long long*)&nxt[(size_t)w * K + k], (unsigned long long)nb);
-                want = true;
-              }
-            }
-          }
-          claim_and_append<CHB>(a, L, nl, ebn, ubn, want, w);
-        }
-      }
-    } else {
+    if (bu) {
       ++bu_levels;
-      for (int32_t g = gw; g < a.ngu; g += nw) {
-        const int2 gu = a.gu[g];
+      const int64_t ni = (int64_t)a.ngu * K;
+      for (int64_t i = gw; i < ni; i += nw) {
+        const int32_t q = (int32_t)(i / K);
+        const int k = (int)(i - (int64_t)q * K);
+        const int2 gu = a.gu[q];
         const int32_t w = gu.x;
-        uint64_t vk[K];
-        bool done = true;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          vk[k] = a.vis[(size_t)w * K + k] | cur[(size_t)w * K + k];
-          done &= (vk[k] & EL[k]) == EL[k];
-        }
-        if (done) continue;  // every edge lane already reached w (uniform)
+        const size_t wk = (size_t)w * K + k;
+        const uint64_t EL = a.edge_lanes[k];
+        const uint64_t vk = a.vis[wk] | cur[wk];
+        if ((vk & EL) == EL) continue;  // every edge lane of the word already reached w (uniform)
         const int32_t re = rp[w + 1];
         const int32_t beg = rp[w] + gu.y * CHB;
         const int32_t end = min(re, beg + CHB);
-        uint64_t orr[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) orr[k] = 0;
-        for (int32_t off = beg + lane; off < end; off += kWave) {
-          const int32_t v = ci[off];
-#pragma unroll
-          for (int k = 0; k < K; ++k) orr[k] |= cur[(size_t)v * K + k];
-        }
-        bool want = false;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const uint64_t nb = wave_or_u64(orr[k]) & EL[k] & ~vk[k];
-          if (nb) {
-            if (lane == 0) atomicOr((unsigned long long*)&nxt[(size_t)w * K + k], (unsigned long long)nb);
-            want = true;
-          }
-        }
-        claim_and_append<CHB>(a, L, nl, ebn, ubn, want && lane == 0, w);
+        uint64_t orr = 0;
+        for (int32_t off = beg + lane; off < end; off += kWave) orr |= cur[(size_t)ci[off] * K + k];
+        const uint64_t nb = wave_or_u64(orr) & EL & ~vk;
+        bool claimed = false;
+        if (nb && lane == 0) claimed = atomicOr((unsigned long long*)&nxt[wk], (unsigned long long)nb) == 0ull;
+        stage_append(a, st, nl, ebn, ubn, claimed, bentry(w, k));
       }
     }
     if (a.has_derived) {
       // 2-degree derived lanes: elementwise over the level-kl entries (Lemma 1)
-      for (int32_t e = ebase + gw; e < ebn; e += nw) {
-        const int32_t v = a.Q[e];
-        bool want = false;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const uint64_t ck = cur[(size_t)v * K + k];
-          const uint64_t reached = a.vis[(size_t)v * K + k] | ck;
-          const int pa = a.lane_pa[64 * k + lane], pb = a.lane_pb[64 * k + lane];
-          bool mine = false;
-          if (pa >= 0) mine = ((((ck >> pa) | (ck >> pb)) & 1ull) != 0) && (((reached >> lane) & 1ull) == 0);
-          const uint64_t nb = ballot(mine);
-          if (nb) {
-            if (lane == 0) atomicOr((unsigned long long*)&nxt[(size_t)v * K + k], (unsigned long long)nb);
-            want = true;
-          }
-        }
-        claim_and_append<CHB>(a, L, nl, ebn, ubn, want && lane == 0, v);
+      for (int64_t i = gw; i < ne; i += nw) {
+        const uint64_t ent = a.Q[ebase + i];
+        const int32_t v = (int32_t)(uint32_t)ent;
+        const int k = (int)(ent >> 32);
+        const size_t vk = (size_t)v * K + k;
+        const uint64_t ck = cur[vk];
+        const uint64_t reached = a.vis[vk] | ck;
+        const int pa = a.lane_pa[64 * k + lane], pb = a.lane_pb[64 * k + lane];
+        bool mine = false;
+        if (pa >= 0) mine = ((((ck >> pa) | (ck >> pb)) & 1ull) != 0) && (((reached >> lane) & 1ull) == 0);
+        const uint64_t nb = ballot(mine);
+        bool claimed = false;
+        if (nb && lane == 0) claimed = atomicOr((unsigned long long*)&nxt[vk], (unsigned long long)nb) == 0ull;
+        stage_append(a, st, nl, ebn, ubn, claimed, bentry(v, k));
       }
     }
     // level kl-2 masks are no longer read: clear them for reuse as level kl+2
     if (kl >= 2) {
-      for (int64_t i = tid; i < (int64_t)(eprev - eprev2) * K; i += nth) {
-        const int32_t v = a.Q[eprev2 + (int32_t)(i / K)];
-        clr[(size_t)v * K + (i % K)] = 0;
+      for (int64_t i = tid; i < (int64_t)(eprev - eprev2); i += nth) {
+        const uint64_t ent = a.Q[eprev2 + i];
+        clr[(size_t)(uint32_t)ent * K + (ent >> 32)] = 0;
       }
     }
-    const uint64_t fsum = wave_sum_u64(C.full);
-    if (lane == 0 && fsum) atomicAdd(a.fulledges, (unsigned long long)fsum);
+    if (lane == 0 && C.full) atomicAdd(&st.full, (unsigned long long)C.full);
     C.full = 0;
+    stage_flush(a, st, nl, ebn, ubn);
     grid_barrier(a.bar);
     eprev2 = eprev;
     eprev = ebase;
@@ -566,36 +622,49 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchArgs a) {
   }
   const int depth = kl - 1;
 
-  // publish forward counters and component sizes
+  // ---- forward counters (workgroup first) and component sizes
   {
-    const uint64_t r0 = wave_sum_u64(C.reached), r1 = wave_sum_u64(C.rnnz), r2 = wave_sum_u64(C.dag);
+    const uint64_t dag = wave_sum_u64(C.dag);  // per lane; the other counters are uniform
     if (lane == 0) {
-      if (r0) atomicAdd(&a.stats[kStReached], (unsigned long long)r0);
-      if (r1) atomicAdd(&a.stats[kStReachedNnz], (unsigned long long)r1);
-      if (r2) atomicAdd(&a.stats[kStDag], (unsigned long long)r2);
+      if (C.reached) atomicAdd(&st.ctr[0], (unsigned long long)C.reached);
+      if (C.rnnz) atomicAdd(&st.ctr[1], (unsigned long long)C.rnnz);
+      if (dag) atomicAdd(&st.ctr[2], (unsigned long long)dag);
     }
-    if (a.has_own) {
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (C.ns[k]) atomicAdd(&a.lane_ns[64 * k + lane], (unsigned long long)C.ns[k]);
+  }
+  if (a.has_own && !failed) {
+    // n_s of each lane: 1 + omega over the vertices the lane reached
+    const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
+    const int64_t v0 = (int64_t)blockIdx.x * per;
+    const int64_t v1 = min((int64_t)n, v0 + per);
+    for (int k = wib; k < K; k += kWavesPB) {
+      unsigned long long acc = 0;
+      for (int64_t v = v0; v < v1; ++v)
+        if ((a.vis[(size_t)v * K + k] >> lane) & 1ull) acc += 1 + (a.omega ? (unsigned long long)a.omega[v] : 0ull);
+      if (acc) atomicAdd(&a.lane_ns[64 * k + lane], acc);
     }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (st.ctr[0]) atomicAdd(&a.stats[kStReached], st.ctr[0]);
+    if (st.ctr[1]) atomicAdd(&a.stats[kStReachedNnz], st.ctr[1]);
+    if (st.ctr[2]) atomicAdd(&a.stats[kStDag], st.ctr[2]);
   }
   grid_barrier(a.bar);
 
   // lanes whose count wrapped (and lanes derived from them) take no part in
   // the backward sweep; the host reruns them in extended form
-  uint64_t X[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    X[k] = ballot(__hip_atomic_load(&a.lane_ovf[64 * k + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0);
+  for (int k = wib; k < K; k += kWavesPB) {
+    uint64_t X = ballot(__hip_atomic_load(&a.lane_ovf[64 * k + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0);
     const int pa = a.lane_pa[64 * k + lane], pb = a.lane_pb[64 * k + lane];
-    X[k] |= ballot(pa >= 0 && ((((X[k] >> pa) | (X[k] >> pb)) & 1ull) != 0));
+    X |= ballot(pa >= 0 && ((((X >> pa) | (X >> pb)) & 1ull) != 0));
+    if (lane == 0) st.sX[k] = X;
   }
+  __syncthreads();
 
   if (!failed && (a.sig_out || a.sm_out)) {
     // trace: keep the counts before psi overwrites them
-    for (int64_t i = tid; i < (int64_t)n * B; i += nth) {
-      const int32_t v = (int32_t)(i / B), j = (int32_t)(i % B);
+    for (int64_t i = tid; i < (int64_t)n * (int64_t)B; i += nth) {
+      const int32_t v = (int32_t)(i / (int64_t)B), j = (int32_t)(i % (int64_t)B);
       const bool r = (a.vis[(size_t)v * K + (j >> 6)] >> (j & 63)) & 1ull;
       if (EXT) { a.sm_out[(size_t)j * n + v] = r ? a.sm[i] : 0.0; a.se_out[(size_t)j * n + v] = r ? a.se[i] : 0; }
       else a.sig_out[(size_t)j * n + v] = r ? a.sig[i] : 0ull;
@@ -610,13 +679,13 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchArgs a) {
       uint64_t* own = F(lb);
       uint64_t* clr = F(lb + 2);
       const int32_t ub = a.uoff[lb], ue = a.uoff[lb + 1];
-      for (int32_t u = ub + gw; u < ue; u += nw) backward_unit<EXT, K>(a, a.U[u], cmv, own, lb, depth, X);
+      for (int64_t i = gw; i < ue - ub; i += nw) backward_unit<EXT>(a, a.U[ub + i], cmv, own, lb, depth, st);
       // level lb+2 masks are no longer read
       if (lb + 2 <= depth) {
         const int32_t e0 = a.qoff[lb + 2], e1 = a.qoff[lb + 3];
-        for (int64_t i = tid; i < (int64_t)(e1 - e0) * K; i += nth) {
-          const int32_t v = a.Q[e0 + (int32_t)(i / K)];
-          clr[(size_t)v * K + (i % K)] = 0;
+        for (int64_t i = tid; i < (int64_t)(e1 - e0); i += nth) {
+          const uint64_t ent = a.Q[e0 + i];
+          clr[(size_t)(uint32_t)ent * K + (ent >> 32)] = 0;
         }
       }
       grid_barrier(a.bar);
@@ -625,64 +694,60 @@ __global__ void __launch_bounds__(256) batch_kernel(BatchArgs a) {
 
   // ---- epilogue: own terms of the 1-degree reduction, overflow and failure lists
   if (tid == 0) {
-    if (!failed && a.has_own) {
-      for (int j = 0; j < B; ++j) {
-        const int32_t s = a.lane_src[j];
-        if (s < 0 || a.lane_own[j] == 0 || ((X[j >> 6] >> (j & 63)) & 1ull)) continue;
-        a.slot_bc[a.lane_slot[j]][s] += (double)a.lane_own[j] * ((double)a.lane_ns[j] - 2.0);
-      }
-    }
-    for (int j = 0; j < B; ++j) {
-      if (a.lane_src[j] < 0) continue;
+    for (int j = 0; j < (int)B; ++j) {
+      const int32_t s = a.lane_src[j];
+      if (s < 0) continue;
       if (failed) {
-        const int32_t k = atomicAdd(a.fail_count, 1);
-        a.fail_list[k] = a.lane_src[j];
-      } else if ((X[j >> 6] >> (j & 63)) & 1ull) {
-        const int32_t k = atomicAdd(a.ovf_count, 1);
-        a.ovf_list[k] = a.lane_src[j];
+        const int32_t q = atomicAdd(a.fail_count, 1);
+        a.fail_list[q] = s;
+      } else if ((st.sX[j >> 6] >> (j & 63)) & 1ull) {
+        const int32_t q = atomicAdd(a.ovf_count, 1);
+        a.ovf_list[q] = s;
+      } else if (a.has_own && a.lane_own[j] != 0) {
+        a.pair_bc[(size_t)a.lane_pair[j] * n + s] += (double)a.lane_own[j] * ((double)a.lane_ns[j] - 2.0);
       }
     }
     atomicAdd(&a.stats[kStLevels], (unsigned long long)levels);
     atomicAdd(&a.stats[kStBuLevels], (unsigned long long)bu_levels);
     atomicAdd(&a.stats[kStLaunches], 1ull);
   }
-  grid_barrier(a.bar);  // everything above has read the lane arrays and the level counters
+  grid_barrier(a.bar);  // everything above has read the lane arrays, the level counters and the sums
+  // fold the per-(word, slot) sums into the slots' scores, in word order
+  for (int64_t v = tid; v < n; v += nth) {
+    for (int p = 0; p < a.npairs; ++p) {
+      double* src = a.pair_bc + (size_t)p * n + v;
+      const double t = *src;
+      if (t != 0.0) {
+        a.slot_bc[a.pair_slot[p]][v] += t;
+        *src = 0.0;
+      }
+    }
+  }
   // leave the control state and (unless a trace wants them) the masks clear for the next launch
   if (tid == 0) {
     for (int i = 0; i < 3 && i < a.cap_levels; ++i) a.lc[i] = LevelCtr{0ull, 0, 0, 0ull, 0, 0};
-    *a.gmulti = 0;
     *a.fulledges = 0;
   }
-  for (int64_t j = tid; j < B; j += nth) { a.lane_ns[j] = 0; a.lane_ovf[j] = 0; }
+  for (int64_t j = tid; j < (int64_t)B; j += nth) { a.lane_ns[j] = 0; a.lane_ovf[j] = 0; }
   if (a.clear_at_end) {
     for (int64_t i = tid; i < (int64_t)fms; i += nth) {
       a.vis[i] = 0;
 #pragma unroll
       for (int s = 0; s < kSlots; ++s) a.fm[(size_t)s * fms + i] = 0;
     }
-    for (int64_t i = tid; i < n; i += nth) a.stamp[i] = -1;
-  }
-}
-
-template <bool EXT>
-static const void* batch_fn(int K) {
-  switch (K) {
-    case 1: return (const void*)batch_kernel<EXT, 1>;
-    case 2: return (const void*)batch_kernel<EXT, 2>;
-    case 3: return (const void*)batch_kernel<EXT, 3>;
-    default: return (const void*)batch_kernel<EXT, 4>;
   }
 }
 
 hipError_t launch_batch(const BatchArgs& a, bool ext, int grid, int block, hipStream_t st) {
-  if (a.K < 1 || a.K > 4) return hipErrorInvalidValue;
+  if (a.K < 1 || a.K > kMaxWords || block != kBatchBlock || a.npairs < 0 || a.npairs > a.cap_pairs)
+    return hipErrorInvalidValue;
   void* args[] = {(void*)&a};
-  const void* fn = ext ? batch_fn<true>(a.K) : batch_fn<false>(a.K);
+  const void* fn = ext ? (const void*)batch_kernel<true> : (const void*)batch_kernel<false>;
   return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, 0, st);
 }
 
-hipError_t batch_max_grid(bool ext, int K, int block, int* blocks_per_cu) {
-  const void* fn = ext ? batch_fn<true>(K) : batch_fn<false>(K);
+hipError_t batch_max_grid(bool ext, int block, int* blocks_per_cu) {
+  const void* fn = ext ? (const void*)batch_kernel<true> : (const void*)batch_kernel<false>;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 

@@ -118,8 +118,14 @@ struct LevelCtr {
 // workgroups are spread over the eight XCDs) meet on their own counter,
 // the last of each class on a top counter, and the very last bumps a
 // generation word the others poll.  Counters return to 0 by themselves;
-// the generation only grows.  Every wave publishes its writes with an
-// agent-scope release fence before arriving and acquires after leaving.
+// the generation only grows.  Every wave first waits until its own stores
+// and atomics are performed at the L2 of its XCD; the workgroup's first
+// thread then publishes them to the other XCDs with one agent-scope release
+// fence (an L2 write-back) before arriving, and takes one agent-scope
+// acquire fence (an L1/L2 invalidation, which serves all the workgroup's
+// waves: they run on one CU) after leaving.  A fence in every wave costs a
+// write-back per wave, which dominated the barrier at a thousand
+// workgroups.
 struct alignas(128) BarSlot {
   unsigned v;
   unsigned pad[31];
@@ -131,9 +137,10 @@ struct GridBar {
 };
 
 __device__ __forceinline__ void grid_barrier(GridBar* b) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned nb = gridDim.x;
     const unsigned g = __hip_atomic_load(&b->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned x = blockIdx.x & 7u;
@@ -156,7 +163,6 @@ __device__ __forceinline__ void grid_barrier(GridBar* b) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // Errors raised inside a persistent kernel; the host maps them to bc_status.
@@ -179,6 +185,7 @@ struct Lists {
   int32_t* err;
   const int32_t* rp;
   int32_t cap_entries, cap_units, cap_parts, cap_multi;
+  int32_t words;     // arrival counters per split entry (one per 64-lane word)
 };
 
 __device__ __forceinline__ void raise_err(const Lists& L, int lvl, int32_t code) {
@@ -235,7 +242,7 @@ __device__ __forceinline__ int append_entries(const Lists& L, int lvl, int32_t e
         } else if (pb + nunits > L.cap_parts) {
           raise_err(L, lvl, kErrCapPartials);
         } else {
-          L.arrive[mi] = 0;
+          for (int32_t k = 0; k < L.words; ++k) L.arrive[(size_t)mi * L.words + k] = 0;
           for (int32_t c = 0; c < nunits; ++c) L.U[u + c] = Unit{vtx, c, mi, pb};
         }
       }

@@ -145,17 +145,26 @@ void map_sources(int32_t n, const int32_t* rp, const Pruned* pr, const int32_t* 
 void choose_deg2(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<Group>& groups,
                  std::vector<Triple>* triples) {
   triples->clear();
+  // triples only within one result slot (groups of one query)
+  int nslot = 1;
+  for (const auto& gr : groups) nslot = std::max(nslot, gr.slot + 1);
   std::vector<int32_t> gi((size_t)n, -1);
-  for (size_t i = 0; i < groups.size(); ++i) gi[groups[i].v] = (int32_t)i;
   std::vector<char> used(groups.size(), 0);
-  for (size_t i = 0; i < groups.size(); ++i) {
-    const int32_t c = groups[i].v;
-    if (used[i] || rp[c + 1] - rp[c] != 2) continue;
-    const int32_t a = ci[rp[c]], b = ci[rp[c] + 1];
-    const int32_t ia = gi[a], ib = gi[b];
-    if (ia < 0 || ib < 0 || used[ia] || used[ib]) continue;
-    used[i] = used[ia] = used[ib] = 1;
-    triples->push_back(Triple{ia, ib, (int32_t)i});
+  for (int sl = 0; sl < nslot; ++sl) {
+    for (size_t i = 0; i < groups.size(); ++i)
+      if (groups[i].slot == sl) gi[groups[i].v] = (int32_t)i;
+    for (size_t i = 0; i < groups.size(); ++i) {
+      if (groups[i].slot != sl) continue;
+      const int32_t c = groups[i].v;
+      if (used[i] || rp[c + 1] - rp[c] != 2) continue;
+      const int32_t a = ci[rp[c]], b = ci[rp[c] + 1];
+      const int32_t ia = gi[a], ib = gi[b];
+      if (ia < 0 || ib < 0 || used[ia] || used[ib]) continue;
+      used[i] = used[ia] = used[ib] = 1;
+      triples->push_back(Triple{ia, ib, (int32_t)i});
+    }
+    for (size_t i = 0; i < groups.size(); ++i)
+      if (groups[i].slot == sl) gi[groups[i].v] = -1;
   }
 }
 

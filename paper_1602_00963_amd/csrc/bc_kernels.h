@@ -57,6 +57,12 @@ struct PlainArgs {
   int32_t cap_entries, cap_units, cap_parts, cap_multi, cap_levels;
 };
 
+// Level lists of the batched kernel hold (vertex, word) entries: entry
+// (v, k) is in level l's list when some lane of word k has v on level l.
+// Q entries are k << 32 | v; units carry the word in bits 24.. of `c`.
+__host__ __device__ inline uint64_t bentry(int32_t v, int k) { return ((uint64_t)k << 32) | (uint32_t)v; }
+constexpr int kUnitWordShift = 24;
+
 struct BatchArgs {
   int32_t n;
   int64_t nnz;
@@ -72,16 +78,14 @@ struct BatchArgs {
   int32_t* se;                // [n][64K] extended exponent
   uint64_t* vis;              // [n][K] lanes that reached the vertex
   uint64_t* fm;               // [4][n][K] rotating per-level lane masks
-  int32_t* stamp;             // [n] last level the vertex was appended to
-  int32_t* Q;
-  Unit* U;
-  int32_t* qoff;
-  int32_t* uoff;
-  LevelCtr* lc;
-  double* part_m;             // [slot][K][64]
+  uint64_t* Q;                // (vertex, word) entries, level after level
+  Unit* U;                    // their work units
+  int32_t* qoff;              // [levels] first entry of each level
+  int32_t* uoff;              // [levels] first unit of each level
+  LevelCtr* lc;               // [levels] append counters
+  double* part_m;             // [slot][64] partial sums of split entries (slots level-relative)
   int32_t* part_e;
-  int32_t* arrive;
-  int32_t* gmulti;
+  int32_t* arrive;            // [entries] arrival counters of split entries
   int32_t* err;
   uint32_t* lane_ovf;         // [64K] lanes whose count wrapped
   int32_t* ovf_list;          // sources of wrapped lanes, appended per batch (host reruns them)
@@ -100,27 +104,30 @@ struct BatchArgs {
   const int32_t* lane_own;    // pendant sources represented (own term)
   const int8_t* lane_pa;      // derived lanes: partner lanes (same word), -1 if traversed
   const int8_t* lane_pb;
-  const int8_t* lane_slot;    // result array of each lane (index into slot_bc)
   double* const* slot_bc;     // per-slot score arrays (device), up to 64
+  const int16_t* lane_pair;   // [64K] (word, slot) pair of each lane
+  const int8_t* pair_slot;    // [npairs] slot of each pair; pairs are numbered in word order
+  int32_t npairs, cap_pairs;
+  double* pair_bc;            // [cap_pairs][n] per-pair sums of one launch, zero between launches
   const uint64_t* edge_lanes; // [K] lanes that propagate along edges (active, not derived)
-  const int32_t* l0;          // distinct source vertices of the batch
-  int32_t nl0;
   int32_t has_derived;        // any lane derived from two partner lanes
   int32_t has_own;            // any lane with pendant sources (component sizes needed)
-  unsigned long long* fulledges; // degrees of vertices every edge lane has reached
+  unsigned long long* fulledges; // edges x words whose word's edge lanes have all reached the vertex
   GridBar* bar;
-  int32_t clear_at_end;       // clear masks and stamps before returning (off for traces)
+  int32_t clear_at_end;       // clear the masks before returning (off for traces)
   double alpha;
-  int32_t cap_entries, cap_units, cap_parts, cap_multi, cap_levels;
+  int32_t cap_entries, cap_units, cap_parts, cap_levels;
 };
 
 constexpr int kBatchChunk = 256;
+constexpr int kMaxWords = 16;    // batches of up to 1024 sources
+constexpr int kBatchBlock = 512; // threads per workgroup of the batched kernel
 constexpr int kPlainChunkHost = 64;
 
 hipError_t launch_plain(const PlainArgs& a, bool ext, int grid, int block, hipStream_t st);
 hipError_t plain_max_grid(bool ext, int block, int* blocks_per_cu);
 
 hipError_t launch_batch(const BatchArgs& a, bool ext, int grid, int block, hipStream_t st);
-hipError_t batch_max_grid(bool ext, int K, int block, int* blocks_per_cu);
+hipError_t batch_max_grid(bool ext, int block, int* blocks_per_cu);
 
 }  // namespace bcx

@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
   const int32_t* __restrict__ ci = a.ci;
   int32_t* __restrict__ d = a.d;
   const Lists L{a.Q, a.U, a.lc, a.arrive, a.gmulti, a.err, a.rp,
-                a.cap_entries, a.cap_units, a.cap_parts, a.cap_multi};
+                a.cap_entries, a.cap_units, a.cap_parts, a.cap_multi, 1};
 
   // per-lane counters, reduced once at the end of the forward sweep
   uint64_t c_reached = 0, c_rnnz = 0, c_dag = 0, c_ns = 0;

@@ -89,6 +89,7 @@ void admit(bc_server* s) {
     Resolved r;
     if (resolve_opts(q->g, &o, &r) != BC_OK) { q->status = BC_E_INVALID_ARG; q->done = true; continue; }
     r.cap_factor = r.B;
+    r.max_slots = 64;
     const int64_t ws = (int64_t)graph_ws_bytes(q->g, r);
     if ((int64_t)q->d_bytes + ws > s->cfg.hbm_budget_bytes) {
       q->status = BC_E_REJECTED;
@@ -127,6 +128,7 @@ bool take_job(bc_server* s, Worker* w, Job* job) {
   Resolved r;
   resolve_opts(lead->g, &o, &r);
   r.cap_factor = r.B;  // worst-case level lists: a batch can never run out of them
+  r.max_slots = 64;
   const size_t need = graph_ws_bytes(lead->g, r);
   if (w->ws_bytes < need) {
     const int64_t grow = (int64_t)need - (int64_t)w->ws_bytes;
@@ -194,6 +196,7 @@ void worker_loop(bc_server* s, Worker* w) {
     Resolved r;
     bc_status st = resolve_opts(job.g, &o, &r);
     r.cap_factor = r.B;
+    r.max_slots = 64;
     if (st == BC_OK)
       st = compute_groups(job.g, r, job.lanes, (int64_t)job.lanes.size(), w->ws, w->ws_bytes, w->st,
                           job.slots.data(), (int)job.slots.size(), nullptr);

@@ -54,8 +54,8 @@ def run_bc(bcm, ctx, g, sources=None, prune=False, **opts):
 
 
 MODES = [dict(mode="plain"), dict(mode="batched", batch=64), dict(mode="batched", batch=128),
-         dict(mode="batched", batch=256)]
-MODE_IDS = ["plain", "b64", "b128", "b256"]
+         dict(mode="batched", batch=256), dict(mode="batched", batch=192), dict(mode="batched", batch=1024)]
+MODE_IDS = ["plain", "b64", "b128", "b256", "b192", "b1024"]
 
 
 @pytest.mark.parametrize("opts", MODES, ids=MODE_IDS)
@@ -271,7 +271,7 @@ def test_autotune_leaves_scores_and_results_unchanged(bcm, ctx):
     G = bcm.Graph(ctx, g)
     S = gg.sample(g.non_isolated(), 300, 5)
     tuned = G.autotune(S, budget_ms=20000)
-    assert tuned["batch"] in (64, 128, 192, 256) and tuned["gteps"] > 0
+    assert tuned["batch"] in (64, 128, 256, 512, 1024) and tuned["gteps"] > 0
     assert not G.scores().any()                 # tuning used scratch scores
     G.compute(S, batch=0)                       # the tuned setting
     ref, _ = oracle.bc(g, S)
