@@ -102,7 +102,7 @@ def measured_traffic(workload_name: str):
     return t
 
 
-def copy_calibration(nbytes: int) -> None:
+def copy_calibration(nbytes: int, quiet: bool = False) -> None:
     """A plain device-to-device copy of known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters."""
     import torch
@@ -111,7 +111,84 @@ def copy_calibration(nbytes: int) -> None:
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
+    if not quiet:
+        print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
+
+
+def _counter_rows(d: str):
+    import csv
+    import glob
+    f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    with open(f[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_counters(fetch_dir: str, write_dir: str, wl: str, copy_bytes: int, command: str) -> None:
+    """Per-launch HBM traffic of the batched kernel from two rocprofv3
+    counter runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by
+    what the same counter reads for the copy kernel of known size run in the
+    same process.  Writes profiles/traffic_batch_kernel_<wl>.json and .md."""
+    res = {}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        kern, copy = [], []
+        for r in _counter_rows(d):
+            if r["Counter_Name"] != name:
+                continue
+            v = float(r["Counter_Value"]) * 1024.0
+            if "batch_kernel" in r["Kernel_Name"]:
+                kern.append(v)
+            elif "copy" in r["Kernel_Name"].lower() and v > 0.5 * copy_bytes:
+                copy.append(v)
+        if not kern or not copy:
+            raise SystemExit(f"{name}: missing batch_kernel or copy dispatches")
+        scale = copy_bytes / float(np.median(copy))
+        res[name] = {"kernel_bytes_per_launch_raw": float(np.mean(kern)), "dispatches": len(kern),
+                     "copy_bytes_raw": float(np.median(copy)), "scale": scale,
+                     "kernel_bytes_per_launch": float(np.mean(kern)) * scale}
+    t = {"kernel": "batch_kernel", "workload": wl, "kernel_sha": kernel_sha(),
+         "bytes_per_launch": res["FETCH_SIZE"]["kernel_bytes_per_launch"] + res["WRITE_SIZE"]["kernel_bytes_per_launch"],
+         "fetch": res["FETCH_SIZE"], "write": res["WRITE_SIZE"], "copy_bytes": copy_bytes, "command": command,
+         "source": f"profiles/traffic_batch_kernel_{wl}.md"}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"traffic_batch_kernel_{wl}.json"), "w") as f:
+        json.dump(t, f, indent=1)
+    with open(os.path.join(ROOT, "profiles", f"traffic_batch_kernel_{wl}.md"), "w") as f:
+        f.write(f"# HBM traffic of batch_kernel, workload {wl}\n\n")
+        f.write(f"Counter runs (one per counter, each followed in the same process by a copy of {copy_bytes} bytes):\n\n")
+        f.write(f"    {command}\n\n")
+        f.write("| counter | batch_kernel KiB/dispatch (raw) | dispatches | copy raw bytes | scale | bytes/launch |\n")
+        f.write("|---|---|---|---|---|---|\n")
+        for name in ("FETCH_SIZE", "WRITE_SIZE"):
+            r = res[name]
+            f.write(f"| {name} | {r['kernel_bytes_per_launch_raw'] / 1024:.0f} | {r['dispatches']} | "
+                    f"{r['copy_bytes_raw']:.4g} | {r['scale']:.4f} | {r['kernel_bytes_per_launch']:.4g} |\n")
+        f.write(f"\nTraffic per launch: {t['bytes_per_launch']:.4g} bytes (kernel source sha {t['kernel_sha']}).\n")
+    print(json.dumps(t), flush=True)
+
+
+def summarize_trace(trace_dir: str, name: str, command: str) -> None:
+    """Kernel-time summary (rocprofv3 --kernel-trace --stats) as markdown."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no kernel_stats.csv under {trace_dir}")
+    with open(f[0]) as fh:
+        rows = list(csv.DictReader(fh))
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    out = os.path.join(ROOT, "profiles", f"{name}.md")
+    with open(out, "w") as fo:
+        fo.write(f"# rocprofv3 kernel statistics: {name}\n\n    {command}\n\n")
+        fo.write("| kernel | calls | total ms | average us | min us | max us | % |\n|---|---|---|---|---|---|---|\n")
+        for r in rows:
+            nm = r.get("Name", "")
+            short = nm if len(nm) < 70 else nm[:67] + "..."
+            fo.write(f"| `{short}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |\n")
+    print(open(out).read())
 
 
 def serving_run(bcm, ctx, n_graphs: int, max_scale: int, n_queries: int, rho: float, seed: int = 5):
@@ -214,9 +291,24 @@ def main():
     ap.add_argument("--serving-max-scale", type=int, default=15)
     ap.add_argument("--serving-queries", type=int, default=200)
     ap.add_argument("--serving-rho", type=float, default=0.8)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="after the run, copy this many bytes (scales the traffic counters)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic_batch_kernel_<workload>.json from two counter runs")
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR", help="write profiles/<--profile-name>.md")
+    ap.add_argument("--profile-name", default="")
+    ap.add_argument("--profile-command", default="")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.summarize_counters:
+        _, wl, _, _ = workload(args.config, args.sources)
+        summarize_counters(args.summarize_counters[0], args.summarize_counters[1], wl, args.calibrate_copy,
+                           args.profile_command)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.profile_name, args.profile_command)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -259,7 +351,9 @@ def main():
     st = stats[-1]
     ms_step = wall_ms / args.steps
     gteps = st["te"] / (ms_step / 1e3) / 1e9
-    kern_ms = float(np.median(times))
+    # the batched kernel's own time: HIP events recorded on the launch stream
+    # around every launch, summed by the library (median step)
+    kern_ms = float(np.median([s["kernel_ms"] for s in stats]))
     per_launch_ms = kern_ms / max(st["launches"], 1)
     tn = nnz if not prune else G.stats()["residual_nnz"]
     bytes_run = alg_bytes(n, tn, st["launches"], st)
@@ -276,6 +370,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel_sha": kernel_sha(),
                      "kernel": "batch_kernel" if args.mode == "batched" else "plain_kernel",
                      "avg_launch_ms": round(per_launch_ms, 4), "launches": int(st["launches"]),
+                     "kernel_ms_per_step": round(kern_ms, 2), "event_ms_per_step": round(float(np.median(times)), 2),
                      "alg_bytes_per_launch": round(bytes_run / max(st["launches"], 1)),
                      "bytes_per_te": round(bytes_run / st["raw_te"], 3) if st["raw_te"] else None},
     }
@@ -290,9 +385,10 @@ def main():
         pst, pms = timed_compute(G, ps, stream, mode="plain", deg1=prune)
         pg = pst["te"] / (pms / 1e3) / 1e9
         pbytes = alg_bytes(n, tn, pst["launches"], pst)
+        pk = pst["kernel_ms"]
         out["plain"] = {"gteps": round(pg, 3), "sample_sources": int(len(ps)), "ms": round(pms, 1),
-                        "avg_launch_ms": round(pms / max(pst["launches"], 1), 4),
-                        "achieved_GBs": round(pbytes / (pms / 1e3) / 1e9, 1)}
+                        "avg_launch_ms": round(pk / max(pst["launches"], 1), 4),
+                        "achieved_GBs": round(pbytes / (pk / 1e3) / 1e9, 1)}
         out["batched_over_plain"] = round(gteps / pg, 2)
         log(f"plain: {pg:.2f} GTEPS on {len(ps)} sources")
     if not args.no_serving:
@@ -303,6 +399,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(g, m, args.cpu_budget)
         log(f"cpu: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
+    if args.calibrate_copy:
+        copy_calibration(args.calibrate_copy, quiet=True)
 
 
 if __name__ == "__main__":

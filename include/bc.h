@@ -136,6 +136,8 @@ typedef struct bc_run_stats {
   double te;                /* traversed edges credited: sum over requested sources of m (original graph) */
   double raw_te;            /* traversed sources * m of the traversed graph */
   double ms;                /* wall time of the call, host-measured, ms */
+  double kernel_ms;         /* sum of the kernel launches' durations, timed with HIP events
+                               recorded on the call's stream around each launch, ms */
 } bc_run_stats;
 
 /*

@@ -48,7 +48,7 @@ class RunStats(ctypes.Structure):
                 ("first_overflow", ctypes.c_int32 * 8), ("levels", ctypes.c_int64),
                 ("bottom_up_levels", ctypes.c_int64), ("reached", ctypes.c_int64), ("reached_nnz", ctypes.c_int64),
                 ("dag_edges", ctypes.c_int64), ("launches", ctypes.c_int64), ("te", ctypes.c_double),
-                ("raw_te", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("raw_te", ctypes.c_double), ("ms", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -620,8 +620,45 @@ struct CallOut {
   std::vector<int32_t> ovf;   // overflowed traversal sources
   std::vector<int32_t> fail;  // sources of batches that exceeded a list capacity
   unsigned long long st[kStCount] = {0};
+  double kernel_ms = 0.0;     // summed launch durations
   int err = 0;
+  void merge(const CallOut& o) {
+    for (int i = 0; i < kStCount; ++i) st[i] += o.st[i];
+    kernel_ms += o.kernel_ms;
+  }
 };
+
+// Launch timing: an event pair recorded on the launch stream around each
+// kernel launch; durations are summed when the host next waits for the
+// stream.  One pool per host thread (the server runs batches from several).
+struct LaunchTimer {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  ~LaunchTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  hipError_t mark(hipStream_t st) {
+    if (used == ev.size()) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      ev.push_back(e);
+    }
+    return hipEventRecord(ev[used++], st);
+  }
+  // After the stream has been waited for: adds the pairs' durations.
+  hipError_t collect(double* ms) {
+    for (size_t i = 0; i + 1 < used; i += 2) {
+      float f = 0.f;
+      hipError_t r = hipEventElapsedTime(&f, ev[i], ev[i + 1]);
+      if (r != hipSuccess) return r;
+      *ms += f;
+    }
+    used = 0;
+    return hipSuccess;
+  }
+};
+static thread_local LaunchTimer t_timer;
 
 // Trace destinations (device) for a batch, or nulls.
 struct TraceDev {
@@ -658,6 +695,7 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
                       const std::vector<Group>& groups, const std::vector<Triple>& triples, char* wsbase,
                       int cap_factor, hipStream_t st, double* const* slot_ptrs, int nslots, const TraceDev* tr,
                       CallOut* out, std::vector<int32_t>* trace_lane_vertex) {
+  t_timer.used = 0;
   BatchWs w;
   batch_layout(g->n, g->nnz, r.B, cap_factor, r.max_slots, wsbase, &w);
   HIPCHK(hipMemsetAsync(w.ctl_begin, 0, w.ctl_bytes, st));
@@ -734,9 +772,12 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
         a.sm_out = (ext && tr->sm) ? tr->sm + off : nullptr;
         a.se_out = (ext && tr->se) ? tr->se + off : nullptr;
       }
+      HIPCHK(t_timer.mark(st));
       HIPCHK(launch_batch(a, ext, grid, r.block, st));
+      HIPCHK(t_timer.mark(st));
     }
     HIPCHK(hipStreamSynchronize(st));  // staging buffer reused by the next group
+    HIPCHK(t_timer.collect(&out->kernel_ms));
   }
   int32_t cnt = 0, err = 0, fcnt = 0;
   HIPCHK(hipMemcpyAsync(&cnt, w.ovf_count, sizeof cnt, hipMemcpyDeviceToHost, st));
@@ -756,6 +797,7 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
 
 bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg, const std::vector<Group>& groups,
                     char* wsbase, hipStream_t st, double* bc, double* delta_out, CallOut* out) {
+  t_timer.used = 0;
   PlainWs w;
   plain_layout(g->n, g->nnz, wsbase, &w);
   HIPCHK(hipMemsetAsync(w.ctl_begin, 0, w.ctl_bytes, st));
@@ -801,13 +843,20 @@ bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& t
     a.src = gr.v;
     a.weight = gr.w;
     a.own = gr.own;
+    HIPCHK(t_timer.mark(st));
     HIPCHK(launch_plain(a, ext, grid, r.block, st));
+    HIPCHK(t_timer.mark(st));
+    if (t_timer.used >= 512) {
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(t_timer.collect(&out->kernel_ms));
+    }
   }
   int32_t cnt = 0, err = 0;
   HIPCHK(hipMemcpyAsync(&cnt, w.ovf_count, sizeof cnt, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(&err, w.err, sizeof err, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(out->st, w.stats, sizeof(out->st), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(t_timer.collect(&out->kernel_ms));
   out->err = err;
   out->ovf.resize(std::min<int32_t>(cnt, g->n + 1));
   if (cnt) HIPCHK(hipMemcpy(out->ovf.data(), w.ovf_list, sizeof(int32_t) * out->ovf.size(), hipMemcpyDeviceToHost));
@@ -821,6 +870,7 @@ static void add_stats(bc_run_stats* s, const CallOut& o) {
   s->reached_nnz += (int64_t)o.st[kStReachedNnz];
   s->dag_edges += (int64_t)o.st[kStDag];
   s->launches += (int64_t)o.st[kStLaunches];
+  s->kernel_ms += o.kernel_ms;
 }
 
 // Workspace: the caller's, or the graph's cached one (grown on demand).
@@ -884,7 +934,7 @@ static bc_status run_groups(bc_graph* g, const Resolved& r, bool ext, const Trav
   s = run_batched(g, r2, ext, tg, again, {}, ws, r2.B, st, slots, nslots, nullptr, &o2, nullptr);
   if (s != BC_OK) return s;
   if (!o2.fail.empty()) return fail(BC_E_CAPACITY, "level-list capacity exceeded at worst-case size");
-  for (int i = 0; i < kStCount; ++i) out->st[i] += o2.st[i];
+  out->merge(o2);
   out->ovf.insert(out->ovf.end(), o2.ovf.begin(), o2.ovf.end());
   out->fail.clear();
   return BC_OK;
@@ -922,7 +972,7 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
     CallOut c2;
     s = run_groups(g, r, ext0, tg, rest, {}, workspace, ws_bytes, st, slots, nslots, &c2);
     if (s != BC_OK) return s;
-    for (int i = 0; i < kStCount; ++i) co.st[i] += c2.st[i];
+    co.merge(c2);
     co.ovf.insert(co.ovf.end(), c2.ovf.begin(), c2.ovf.end());
   } else {
     s = run_groups(g, r, ext0, tg, groups, triples, workspace, ws_bytes, st, slots, nslots, &co);
