@@ -21,10 +21,10 @@
 //     on level l-1 (rows gathered several at a time).  2-degree derived
 //     lanes (Lemma 1) take Eq. (6) instead: the sum of the two partner
 //     lanes' counts at w over the partners sitting on level l-1 at w.
-//   top-down discovery of level l+1 -- F_{l+1}(x) |= F_l(w) & ~reached(x),
-//     with reached(x) = vis(x) | F_l(x) (vis is being updated with F_l by
-//     the counting job of the same phase; either value gives the same
-//     result).  Bottom-up levels instead OR, for every (vertex, word) not
+//   top-down discovery of level l+1 -- F_{l+1}(x) |= F_l(w) & ~(F_{l-1}(x)
+//     | F_l(x)): in an undirected graph a neighbour of a level-l vertex is
+//     at distance l-1, l or l+1, so the two level masks the phase reads
+//     anyway tell which lanes have not reached x.  Bottom-up levels instead OR, for every (vertex, word) not
 //     yet reached by all the word's sources, its neighbours' level-l masks.
 //     Derived lanes are not propagated along edges: lane c reaches v at
 //     level l+1 exactly when a partner sits on v at level l and c has not
@@ -253,9 +253,12 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
       if (off < end) {
         vl = ci[off];
         const size_t xk = (size_t)vl * K + k;
-        if (cnt) ml = par[xk] & em;
+        const uint64_t px = par[xk];
+        if (cnt) ml = px & em;
         if (disc) {
-          const uint64_t nb = em & ~(a.vis[xk] | cur[xk]);
+          // a neighbour of a level-kl vertex is at distance kl-1, kl or kl+1
+          // from the lane's source, so "not yet reached" is "on neither level"
+          const uint64_t nb = em & ~(px | cur[xk]);
           if (nb) claimed = atomicOr((unsigned long long*)&nxt[xk], (unsigned long long)nb) == 0ull;
         }
       }
