@@ -123,7 +123,7 @@ struct BatchWs {
   int32_t *fail_list, *fail_count;
   uint64_t *sig, *vis, *fm, *Q;
   double *part_m, *pair_bc;
-  Unit* U;
+  BUnit* U;
   LevelCtr* lc;
   uint32_t* lane_ovf;
   unsigned long long *lane_ns, *stats, *fulledges;
@@ -163,7 +163,7 @@ size_t batch_layout(int64_t n, int64_t nnz, int B, int cap_factor, int max_slots
   t.fm = t.vis ? t.vis + (size_t)n * K : nullptr;
   t.mask_bytes = sizeof(uint64_t) * (size_t)n * K * 5;
   t.Q = c.take<uint64_t>(t.caps.entries);
-  t.U = c.take<Unit>(t.caps.units);
+  t.U = c.take<BUnit>(t.caps.units);
   t.qoff = c.take<int32_t>(n + 3);
   t.uoff = c.take<int32_t>(n + 3);
   t.part_m = c.take<double>((size_t)t.caps.parts * 64);
@@ -224,6 +224,9 @@ struct bc_graph {
   bool tuned = false;
   int32_t tuned_batch = 0, tuned_grid = 0;
   double tuned_alpha = 0.0;
+  // batching order of sources (computed on the first batched call)
+  std::vector<int32_t> rank;
+  std::once_flag rank_once;
   std::mutex mu;
 };
 
@@ -949,6 +952,11 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
   HIPCHK(hipSetDevice(g->ctx->device));
   const TravGraph tg = trav(g, r.deg1);
   std::vector<Triple> triples;
+  if (r.mode == BC_MODE_BATCHED) {
+    // sources close in the graph share words: denser level masks and rows
+    std::call_once(g->rank_once, [g] { g->rank = locality_rank(g->n, g->h_rp.data(), g->h_ci.data()); });
+    order_groups(g->rank, groups);
+  }
   if (r.deg2) choose_deg2(g->n, tg.h_rp, tg.h_ci, groups, &triples);
   bc_run_stats rs{};
   for (int i = 0; i < 8; ++i) rs.first_overflow[i] = -1;

@@ -49,7 +49,6 @@ constexpr int kSlots = 4;                          // rotating level-mask arrays
 constexpr int kStageCap = 2048;                    // staged appends per workgroup and phase
 constexpr int kWavesPB = kBatchBlock / kWave;
 constexpr int kStagePerThread = kStageCap / kBatchBlock;
-constexpr uint32_t kChunkMask = (1u << kUnitWordShift) - 1;
 
 __device__ __forceinline__ int32_t ldr32(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -80,12 +79,14 @@ __device__ __forceinline__ void raise_b(const BatchArgs& a, int lvl, int32_t cod
   atomicOr(a.err, code);
 }
 
-// Writes entry `ent` at list position e with its units at u (partial-sum
-// slots at pb when it spans several units).
+// Writes entry `ent` (its vertex's edges start at rb, deg of them) at list
+// position e with its units at u (partial-sum slots at pb when it spans
+// several units).
 __device__ __forceinline__ void write_entry(const BatchArgs& a, int lvl, int64_t e, int64_t u, int64_t pb,
-                                            uint64_t ent, int32_t nun) {
+                                            uint64_t ent, int32_t rb, int32_t deg) {
   const int32_t v = (int32_t)(uint32_t)ent;
-  const int32_t kw = (int32_t)(ent >> 32) << kUnitWordShift;
+  const int32_t k = (int32_t)(ent >> 32);
+  const int32_t nun = units_of<CHB>(deg);
   if (e >= a.cap_entries) {
     raise_b(a, lvl, kErrCapEntries);
   } else if (u + nun > a.cap_units) {
@@ -95,10 +96,11 @@ __device__ __forceinline__ void write_entry(const BatchArgs& a, int lvl, int64_t
   } else {
     a.Q[e] = ent;
     if (nun == 1) {
-      a.U[u] = Unit{v, kw, -1, 0};
+      a.U[u] = BUnit{v, rb, rb + deg, deg, k, 0, -1, 0};
     } else {
       a.arrive[e] = 0;
-      for (int32_t c = 0; c < nun; ++c) a.U[u + c] = Unit{v, kw | c, (int32_t)e, (int32_t)pb};
+      for (int32_t c = 0; c < nun; ++c)
+        a.U[u + c] = BUnit{v, rb + c * CHB, min(rb + deg, rb + (c + 1) * CHB), deg, k, c, (int32_t)e, (int32_t)pb};
     }
   }
 }
@@ -107,10 +109,11 @@ __device__ __forceinline__ void write_entry(const BatchArgs& a, int lvl, int64_t
 __device__ __forceinline__ void global_append(const BatchArgs& a, int lvl, int32_t ebase, int32_t ubase, bool want,
                                            uint64_t ent) {
   if (ballot(want) == 0) return;
-  int32_t deg = 0, nun = 0;
+  int32_t deg = 0, nun = 0, rb = 0;
   if (want) {
     const int32_t v = (int32_t)(uint32_t)ent;
-    deg = a.rp[v + 1] - a.rp[v];
+    rb = a.rp[v];
+    deg = a.rp[v + 1] - rb;
     nun = units_of<CHB>(deg);
   }
   const uint64_t contrib = want ? ((1ull << 32) | (uint64_t)(uint32_t)nun) : 0ull;
@@ -128,7 +131,7 @@ __device__ __forceinline__ void global_append(const BatchArgs& a, int lvl, int32
     int64_t pb = 0;
     if (nun > 1) pb = atomicAdd(&a.lc[lvl].pslots, nun);
     write_entry(a, lvl, (int64_t)ebase + (int64_t)(my >> 32), (int64_t)ubase + (int64_t)(my & 0xffffffffull), pb,
-                ent, nun);
+                ent, rb, deg);
   }
 }
 
@@ -196,7 +199,9 @@ __device__ __forceinline__ void stage_flush(const BatchArgs& a, Stage& st, int l
     for (int r = 0; r < kStagePerThread; ++r) {
       const int i = t * kStagePerThread + r;
       if (i < cnt) {
-        write_entry(a, lvl, (int64_t)ebase + st.base_e + i, uo, po, st.e[i], nun[r]);
+        const int32_t v = (int32_t)(uint32_t)st.e[i];
+        const int32_t rb = a.rp[v];
+        write_entry(a, lvl, (int64_t)ebase + st.base_e + i, uo, po, st.e[i], rb, a.rp[v + 1] - rb);
         uo += nun[r];
         if (nun[r] > 1) po += nun[r];
       }
@@ -220,7 +225,7 @@ struct Ctr {
 // A unit of level kl: counting of level kl (when `count`) and top-down
 // discovery of level kl+1 (when `td`).
 template <bool EXT>
-__device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, const Unit& un, const uint64_t* par,
+__device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, const BUnit& un, const uint64_t* par,
                                              const uint64_t* cur, uint64_t* nxt, int kl, bool count, bool td,
                                              int32_t ebn, int32_t ubn, Ctr& C) {
   constexpr int G = EXT ? 8 : 16;  // neighbour rows loaded before any is consumed
@@ -229,10 +234,7 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
   const int lane = lane_id();
   const int32_t* __restrict__ rp = a.rp;
   const int32_t* __restrict__ ci = a.ci;
-  const int32_t w = un.v;
-  const int k = (int)((uint32_t)un.c >> kUnitWordShift);
-  const int32_t c = (int32_t)((uint32_t)un.c & kChunkMask);
-  const int32_t rb = rp[w], re = rp[w + 1];
+  const int32_t w = un.v, k = un.k, c = un.c, deg = un.deg;
   const size_t wk = (size_t)w * K + k;
   const uint64_t EL = a.edge_lanes[k];
   const uint64_t nbm = cur[wk];  // lanes of word k on level kl at w
@@ -243,8 +245,7 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
   Ext x = ext_zero();
   bool wrap = false;
   if (cnt || disc) {
-    const int32_t beg = rb + c * CHB;
-    const int32_t end = min(re, beg + CHB);
+    const int32_t beg = un.beg, end = un.end;
     for (int32_t off0 = beg; off0 < end; off0 += kWave) {
       const int32_t off = off0 + lane;
       int32_t vl = 0;
@@ -312,7 +313,7 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
   if (!count) return;
   // combine the units of a split entry in unit order (the last arriving wave)
   if (un.mi >= 0) {
-    const int32_t nunits = units_of<CHB>(re - rb);
+    const int32_t nunits = units_of<CHB>(deg);
     const size_t pi = (size_t)(un.pb + c) * 64 + lane;
     if (EXT) { a.part_m[pi] = x.m; a.part_e[pi] = x.e; }
     else { a.part_m[pi] = __longlong_as_double((long long)s); a.part_e[pi] = wrap ? 1 : 0; }
@@ -376,17 +377,17 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
     const uint64_t nv = ov | nbm;
     a.vis[wk] = nv;
     // edges of word k no source of the word can still discover
-    if ((nv & EL) == EL && (ov & EL) != EL) C.full += (uint64_t)(re - rb);
+    if ((nv & EL) == EL && (ov & EL) != EL) C.full += (uint64_t)deg;
   }
   const uint64_t pc = (uint64_t)__popcll(nbm);
   C.reached += pc;
-  C.rnnz += pc * (uint64_t)(re - rb);
+  C.rnnz += pc * (uint64_t)deg;
 }
 
 // ----------------------------------------------------------- backward unit
 
 template <bool EXT>
-__device__ __forceinline__ void backward_unit(const BatchArgs& a, const Unit& un, const uint64_t* cmv, uint64_t* own,
+__device__ __forceinline__ void backward_unit(const BatchArgs& a, const BUnit& un, const uint64_t* cmv, uint64_t* own,
                                               int lb, int depth, const Stage& st) {
   constexpr int G = EXT ? 8 : 16;
   const int K = a.K;
@@ -395,10 +396,7 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const Unit& un
   const int32_t* __restrict__ rp = a.rp;
   const int32_t* __restrict__ ci = a.ci;
   double* psi = EXT ? a.sm : (double*)a.sig;
-  const int32_t w = un.v;
-  const int k = (int)((uint32_t)un.c >> kUnitWordShift);
-  const int32_t c = (int32_t)((uint32_t)un.c & kChunkMask);
-  const int32_t rb = rp[w], re = rp[w + 1];
+  const int32_t w = un.v, k = un.k, c = un.c;
   const size_t wk = (size_t)w * K + k;
   const size_t idx = (size_t)w * B + 64 * k + lane;
   const bool r = (a.vis[wk] >> lane) & 1ull;
@@ -407,8 +405,7 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const Unit& un
   double acc = 0.0;
   if (om && lb < depth) {
     const int32_t ew = (EXT && ((om >> lane) & 1ull)) ? a.se[idx] : 0;
-    const int32_t beg = rb + c * CHB;
-    const int32_t end = min(re, beg + CHB);
+    const int32_t beg = un.beg, end = un.end;
     for (int32_t off0 = beg; off0 < end; off0 += kWave) {
       const int32_t off = off0 + lane;
       int32_t vl = 0;
@@ -445,7 +442,7 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const Unit& un
     }
   }
   if (un.mi >= 0) {
-    const int32_t nunits = units_of<CHB>(re - rb);
+    const int32_t nunits = units_of<CHB>(un.deg);
     a.part_m[(size_t)(un.pb + c) * 64 + lane] = acc;
     fence_release();
     int32_t prev = 0;
@@ -562,8 +559,14 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     }
     ++levels;
     if (kl >= 1 || !bu) {
-      for (int64_t i = gw; i < nu; i += nw)
-        forward_unit<EXT>(a, st, a.U[ubase + i], par, cur, nxt, kl, kl >= 1, !bu, ebn, ubn, C);
+      // the next unit's record is fetched while this one is worked on
+      BUnit nx{};
+      if (gw < nu) nx = a.U[ubase + gw];
+      for (int64_t i = gw; i < nu; i += nw) {
+        const BUnit un = nx;
+        if (i + nw < nu) nx = a.U[ubase + i + nw];
+        forward_unit<EXT>(a, st, un, par, cur, nxt, kl, kl >= 1, !bu, ebn, ubn, C);
+      }
     }
     if (bu) {
       ++bu_levels;
@@ -682,7 +685,13 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
       uint64_t* own = F(lb);
       uint64_t* clr = F(lb + 2);
       const int32_t ub = a.uoff[lb], ue = a.uoff[lb + 1];
-      for (int64_t i = gw; i < ue - ub; i += nw) backward_unit<EXT>(a, a.U[ub + i], cmv, own, lb, depth, st);
+      BUnit nx{};
+      if (gw < ue - ub) nx = a.U[ub + gw];
+      for (int64_t i = gw; i < ue - ub; i += nw) {
+        const BUnit un = nx;
+        if (i + nw < ue - ub) nx = a.U[ub + i + nw];
+        backward_unit<EXT>(a, un, cmv, own, lb, depth, st);
+      }
       // level lb+2 masks are no longer read
       if (lb + 2 <= depth) {
         const int32_t e0 = a.qoff[lb + 2], e1 = a.qoff[lb + 3];

@@ -168,4 +168,39 @@ void choose_deg2(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<Gr
   }
 }
 
+std::vector<int32_t> locality_rank(int32_t n, const int32_t* rp, const int32_t* ci) {
+  std::vector<int32_t> rank((size_t)n, -1), queue;
+  queue.reserve((size_t)n);
+  int32_t next = 0;
+  auto bfs = [&](int32_t s) {
+    rank[s] = next++;
+    size_t head = queue.size();
+    queue.push_back(s);
+    while (head < queue.size()) {
+      const int32_t v = queue[head++];
+      for (int32_t e = rp[v]; e < rp[v + 1]; ++e) {
+        const int32_t x = ci[e];
+        if (rank[x] < 0) {
+          rank[x] = next++;
+          queue.push_back(x);
+        }
+      }
+    }
+  };
+  int32_t hub = 0;
+  for (int32_t v = 1; v < n; ++v)
+    if (rp[v + 1] - rp[v] > rp[hub + 1] - rp[hub]) hub = v;
+  if (n > 0) bfs(hub);
+  for (int32_t v = 0; v < n; ++v)
+    if (rank[v] < 0) bfs(v);
+  return rank;
+}
+
+void order_groups(const std::vector<int32_t>& rank, std::vector<Group>& groups) {
+  std::stable_sort(groups.begin(), groups.end(), [&](const Group& a, const Group& b) {
+    if (a.slot != b.slot) return a.slot < b.slot;
+    return rank[a.v] < rank[b.v];
+  });
+}
+
 }  // namespace bcx

@@ -39,6 +39,15 @@ void prune_deg1(int32_t n, const int32_t* rp, const int32_t* ci, Pruned* out);
 // sources that are not isolated.
 void map_sources(int32_t n, const int32_t* rp, const Pruned* pr, const int32_t* src, int64_t k,
                  std::vector<Group>* groups, int64_t* credited);
+// Locality ranking of the vertices for batching: breadth-first discovery
+// order, starting from the highest-degree vertex, then each remaining
+// component.  Sources adjacent in this order are close in the graph, so the
+// 64 sources of a word sit on nearby levels of every vertex.
+std::vector<int32_t> locality_rank(int32_t n, const int32_t* rp, const int32_t* ci);
+
+// Orders groups by (result slot, rank of their vertex).
+void order_groups(const std::vector<int32_t>& rank, std::vector<Group>& groups);
+
 void choose_deg2(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<Group>& groups,
                  std::vector<Triple>* triples);
 

@@ -59,9 +59,16 @@ struct PlainArgs {
 
 // Level lists of the batched kernel hold (vertex, word) entries: entry
 // (v, k) is in level l's list when some lane of word k has v on level l.
-// Q entries are k << 32 | v; units carry the word in bits 24.. of `c`.
+// Q entries are k << 32 | v.
 __host__ __device__ inline uint64_t bentry(int32_t v, int k) { return ((uint64_t)k << 32) | (uint32_t)v; }
-constexpr int kUnitWordShift = 24;
+
+// A work unit of the batched kernel: edges [beg, end) of vertex v, for the
+// 64 sources of word k; chunk c of an entry that spans several units also
+// carries the entry's arrival counter mi and partial-sum slot base pb.
+struct BUnit {
+  int32_t v, beg, end, deg;
+  int32_t k, c, mi, pb;
+};
 
 struct BatchArgs {
   int32_t n;
@@ -79,7 +86,7 @@ struct BatchArgs {
   uint64_t* vis;              // [n][K] lanes that reached the vertex
   uint64_t* fm;               // [4][n][K] rotating per-level lane masks
   uint64_t* Q;                // (vertex, word) entries, level after level
-  Unit* U;                    // their work units
+  BUnit* U;                   // their work units
   int32_t* qoff;              // [levels] first entry of each level
   int32_t* uoff;              // [levels] first unit of each level
   LevelCtr* lc;               // [levels] append counters
