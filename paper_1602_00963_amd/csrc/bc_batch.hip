@@ -235,6 +235,9 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
   const int32_t* __restrict__ rp = a.rp;
   const int32_t* __restrict__ ci = a.ci;
   const int32_t w = un.v, k = un.k, c = un.c, deg = un.deg;
+  const int32_t beg = un.beg, end = un.end;
+  // the first chunk's neighbours are fetched with the unit's own masks
+  const int32_t vl0 = beg + lane < end ? ci[beg + lane] : 0;
   const size_t wk = (size_t)w * K + k;
   const uint64_t EL = a.edge_lanes[k];
   const uint64_t nbm = cur[wk];  // lanes of word k on level kl at w
@@ -245,14 +248,13 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
   Ext x = ext_zero();
   bool wrap = false;
   if (cnt || disc) {
-    const int32_t beg = un.beg, end = un.end;
     for (int32_t off0 = beg; off0 < end; off0 += kWave) {
       const int32_t off = off0 + lane;
       int32_t vl = 0;
       uint64_t ml = 0;
       bool claimed = false;
       if (off < end) {
-        vl = ci[off];
+        vl = off0 == beg ? vl0 : ci[off];
         const size_t xk = (size_t)vl * K + k;
         const uint64_t px = par[xk];
         if (cnt) ml = px & em;
@@ -397,21 +399,29 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const BUnit& u
   const int32_t* __restrict__ ci = a.ci;
   double* psi = EXT ? a.sm : (double*)a.sig;
   const int32_t w = un.v, k = un.k, c = un.c;
+  const int32_t beg = un.beg, end = un.end;
   const size_t wk = (size_t)w * K + k;
   const size_t idx = (size_t)w * B + 64 * k + lane;
-  const bool r = (a.vis[wk] >> lane) & 1ull;
-  const uint64_t om = ballot(r && a.lv[idx] == lb) & ~st.sX[k];
+  // issued together: the first chunk's neighbours, the unit's lanes and
+  // levels, and what the lanes' dependencies will need
+  const int32_t vl0 = beg + lane < end ? ci[beg + lane] : 0;
+  const uint64_t vw = a.vis[wk];
+  const int32_t lvw = a.lv[idx];
+  const double sw = EXT ? a.sm[idx] : (double)a.sig[idx];
+  const double lw = a.lane_w[64 * k + lane];
+  const int pr = a.lane_pair[64 * k + lane];
+  const bool r = (vw >> lane) & 1ull;
+  const uint64_t om = ballot(r && lvw == lb) & ~st.sX[k];
   if (c == 0 && lane == 0) own[wk] = om;
   double acc = 0.0;
   if (om && lb < depth) {
     const int32_t ew = (EXT && ((om >> lane) & 1ull)) ? a.se[idx] : 0;
-    const int32_t beg = un.beg, end = un.end;
     for (int32_t off0 = beg; off0 < end; off0 += kWave) {
       const int32_t off = off0 + lane;
       int32_t vl = 0;
       uint64_t ml = 0;
       if (off < end) {
-        vl = ci[off];
+        vl = off0 == beg ? vl0 : ci[off];
         ml = cmv[(size_t)vl * K + k] & om;
       }
       uint64_t act = ballot(ml != 0);
@@ -459,14 +469,12 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const BUnit& u
   const double omw = a.omega ? (double)a.omega[w] : 0.0;
   double cs = 0.0;
   if ((om >> lane) & 1ull) {
-    const double sw = EXT ? a.sm[idx] : (double)a.sig[idx];
     const double delta = sw * acc;
     psi[idx] = (1.0 + delta + omw) / sw;
-    cs = a.lane_w[64 * k + lane] * (delta + omw);
+    cs = lw * (delta + omw);
     if (a.delta_out) a.delta_out[(size_t)(64 * k + lane) * a.n + w] = delta;
   }
   // per (word, slot) sums in lane order
-  const int pr = a.lane_pair[64 * k + lane];
   uint64_t rem = om;
   while (rem) {
     const int pv = __builtin_amdgcn_readlane(pr, __builtin_ctzll(rem));
