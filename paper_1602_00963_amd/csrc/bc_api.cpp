@@ -121,7 +121,7 @@ BatchCaps batch_caps(int64_t n, int64_t nnz, int B, int cap_factor) {
 struct BatchWs {
   int32_t *lv, *se, *qoff, *uoff, *part_e, *arrive, *err, *ovf_list, *ovf_count;
   int32_t *fail_list, *fail_count;
-  uint64_t *sig, *vis, *fm, *Q;
+  uint64_t *sig, *vis, *fm, *Q, *emask;
   double *part_m, *pair_bc;
   BUnit* U;
   LevelCtr* lc;
@@ -169,6 +169,7 @@ size_t batch_layout(int64_t n, int64_t nnz, int B, int cap_factor, int max_slots
   t.part_m = c.take<double>((size_t)t.caps.parts * 64);
   t.part_e = c.take<int32_t>((size_t)t.caps.parts * 64);
   t.arrive = c.take<int32_t>(t.caps.entries);
+  t.emask = c.take<uint64_t>(t.caps.entries);
   t.cap_pairs = cap_pairs_for(K, max_slots);
   t.pair_bc = c.take<double>((size_t)t.cap_pairs * n);
   t.ovf_list = c.take<int32_t>(n + 1);
@@ -734,6 +735,7 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   a.part_m = w.part_m;
   a.part_e = w.part_e;
   a.arrive = w.arrive;
+  a.emask = w.emask;
   a.err = w.err;
   a.lane_ovf = w.lane_ovf;
   a.ovf_list = w.ovf_list;
@@ -745,6 +747,7 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   a.fulledges = w.fulledges;
   a.bar = w.bar;
   a.clear_at_end = tr ? 0 : 1;
+  a.keep_lv = tr ? 1 : 0;
   a.alpha = r.alpha;
   a.cap_entries = (int32_t)w.caps.entries;
   a.cap_units = (int32_t)w.caps.units;

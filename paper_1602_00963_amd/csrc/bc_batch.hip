@@ -96,7 +96,7 @@ __device__ __forceinline__ void write_entry(const BatchArgs& a, int lvl, int64_t
   } else {
     a.Q[e] = ent;
     if (nun == 1) {
-      a.U[u] = BUnit{v, rb, rb + deg, deg, k, 0, -1, 0};
+      a.U[u] = BUnit{v, rb, rb + deg, deg, k, 0, (int32_t)e, 0};
     } else {
       a.arrive[e] = 0;
       for (int32_t c = 0; c < nun; ++c)
@@ -314,14 +314,14 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
   }
   if (!count) return;
   // combine the units of a split entry in unit order (the last arriving wave)
-  if (un.mi >= 0) {
+  if (deg > CHB) {
     const int32_t nunits = units_of<CHB>(deg);
     const size_t pi = (size_t)(un.pb + c) * 64 + lane;
     if (EXT) { a.part_m[pi] = x.m; a.part_e[pi] = x.e; }
     else { a.part_m[pi] = __longlong_as_double((long long)s); a.part_e[pi] = wrap ? 1 : 0; }
     fence_release();
     int32_t prev = 0;
-    if (lane == 0) prev = atomicAdd(&a.arrive[un.mi], 1);
+    if (lane == 0) prev = atomicAdd(&a.arrive[un.e], 1);
     prev = __shfl(prev, 0, kWave);
     if (prev != nunits - 1) return;
     fence_acquire();
@@ -372,9 +372,10 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
       a.sig[idx] = s;
       if (wrap) atomicOr(&a.lane_ovf[64 * k + lane], 1u);
     }
-    a.lv[idx] = kl;
+    if (a.keep_lv) a.lv[idx] = kl;
   }
   if (lane == 0) {
+    a.emask[un.e] = nbm;
     const uint64_t ov = a.vis[wk];
     const uint64_t nv = ov | nbm;
     a.vis[wk] = nv;
@@ -405,13 +406,10 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const BUnit& u
   // issued together: the first chunk's neighbours, the unit's lanes and
   // levels, and what the lanes' dependencies will need
   const int32_t vl0 = beg + lane < end ? ci[beg + lane] : 0;
-  const uint64_t vw = a.vis[wk];
-  const int32_t lvw = a.lv[idx];
+  const uint64_t om = a.emask[un.e] & ~st.sX[k];  // the word's lanes on level lb at w
   const double sw = EXT ? a.sm[idx] : (double)a.sig[idx];
   const double lw = a.lane_w[64 * k + lane];
   const int pr = a.lane_pair[64 * k + lane];
-  const bool r = (vw >> lane) & 1ull;
-  const uint64_t om = ballot(r && lvw == lb) & ~st.sX[k];
   if (c == 0 && lane == 0) own[wk] = om;
   double acc = 0.0;
   if (om && lb < depth) {
@@ -451,12 +449,12 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const BUnit& u
       }
     }
   }
-  if (un.mi >= 0) {
+  if (un.deg > CHB) {
     const int32_t nunits = units_of<CHB>(un.deg);
     a.part_m[(size_t)(un.pb + c) * 64 + lane] = acc;
     fence_release();
     int32_t prev = 0;
-    if (lane == 0) prev = atomicAdd(&a.arrive[un.mi], 1);
+    if (lane == 0) prev = atomicAdd(&a.arrive[un.e], 1);
     prev = __shfl(prev, 0, kWave);
     if (prev != 2 * nunits - 1) return;  // the forward counting phase took the first nunits arrivals
     fence_acquire();
@@ -522,7 +520,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
       if (s >= 0) {
         const int j = (int)tid;
         const uint64_t bit = 1ull << (j & 63);
-        a.lv[(size_t)s * B + j] = 0;
+        if (a.keep_lv) a.lv[(size_t)s * B + j] = 0;
         if (EXT) { a.sm[(size_t)s * B + j] = 1.0; a.se[(size_t)s * B + j] = 0; }
         else a.sig[(size_t)s * B + j] = 1ull;
         atomicOr((unsigned long long*)&a.vis[(size_t)s * K + (j >> 6)], (unsigned long long)bit);

@@ -62,12 +62,13 @@ struct PlainArgs {
 // Q entries are k << 32 | v.
 __host__ __device__ inline uint64_t bentry(int32_t v, int k) { return ((uint64_t)k << 32) | (uint32_t)v; }
 
-// A work unit of the batched kernel: edges [beg, end) of vertex v, for the
-// 64 sources of word k; chunk c of an entry that spans several units also
-// carries the entry's arrival counter mi and partial-sum slot base pb.
+// A work unit of the batched kernel: edges [beg, end) of vertex v (degree
+// deg), for the 64 sources of word k, belonging to level-list entry e;
+// an entry of degree > 256 spans several units (chunk c) that combine their
+// partial sums in slots pb + c.
 struct BUnit {
   int32_t v, beg, end, deg;
-  int32_t k, c, mi, pb;
+  int32_t k, c, e, pb;
 };
 
 struct BatchArgs {
@@ -79,7 +80,8 @@ struct BatchArgs {
   const int32_t* omega;
   const int2* gu;             // static units (vertex, chunk) for bottom-up levels
   int32_t ngu;
-  int32_t* lv;                // [n][64K] level per (vertex, lane), valid where vis bit set
+  int32_t* lv;                // [n][64K] level per (vertex, lane), kept for traces only
+  int32_t keep_lv;            // write lv (traces)
   uint64_t* sig;              // [n][64K] exact counts; psi overwrites them in the backward sweep
   double* sm;                 // [n][64K] extended significand (psi overwrites)
   int32_t* se;                // [n][64K] extended exponent
@@ -93,6 +95,7 @@ struct BatchArgs {
   double* part_m;             // [slot][64] partial sums of split entries (slots level-relative)
   int32_t* part_e;
   int32_t* arrive;            // [entries] arrival counters of split entries
+  uint64_t* emask;            // [entries] lanes of the entry's word on its level, set when counted
   int32_t* err;
   uint32_t* lane_ovf;         // [64K] lanes whose count wrapped
   int32_t* ovf_list;          // sources of wrapped lanes, appended per batch (host reruns them)
