@@ -49,6 +49,7 @@ constexpr int kSlots = 4;                          // rotating level-mask arrays
 constexpr int kStageCap = 2048;                    // staged appends per workgroup and phase
 constexpr int kWavesPB = kBatchBlock / kWave;
 constexpr int kStagePerThread = kStageCap / kBatchBlock;
+constexpr int kLaneMaxDeg = 32;                    // longest adjacency a single lane walks
 
 __device__ __forceinline__ int32_t ldr32(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -69,6 +70,7 @@ struct Stage {
   int32_t n;              // entries staged (may pass kStageCap: the rest went straight to the list)
   int32_t base_e, base_u, base_p;
   unsigned long long full;
+  unsigned long long newl;  // lanes discovered by the workgroup in this phase
   uint64_t wu[kWavesPB], wp[kWavesPB], wd[kWavesPB];
   uint64_t sX[kMaxWords];
   unsigned long long ctr[3];
@@ -211,13 +213,34 @@ __device__ __forceinline__ void stage_flush(const BatchArgs& a, Stage& st, int l
   if (t == 0) {
     st.n = 0;
     if (st.full) atomicAdd(a.fulledges, st.full);
+    if (st.newl) atomicAdd(&a.lc[lvl].lanes, st.newl);
     st.full = 0;
+    st.newl = 0;
   }
 }
 
-// Per-wave run counters (dag per lane, the others uniform).
+// Appends one entry from a single lane (divergent code): a slot of the
+// workgroup's stage, or straight to the list when the stage is full.
+__device__ __forceinline__ void lane_append(const BatchArgs& a, Stage& st, int lvl, int32_t ebase, int32_t ubase,
+                                            uint64_t ent) {
+  const int pos = atomicAdd(&st.n, 1);
+  if (pos < kStageCap) {
+    st.e[pos] = ent;
+    return;
+  }
+  const int32_t v = (int32_t)(uint32_t)ent;
+  const int32_t rb = a.rp[v], deg = a.rp[v + 1] - rb;
+  const int32_t nun = units_of<CHB>(deg);
+  const unsigned long long b = atomicAdd(&a.lc[lvl].packed, (1ull << 32) | (unsigned long long)(uint32_t)nun);
+  atomicAdd(&a.lc[lvl].fedges, (unsigned long long)deg);
+  const int64_t pb = nun > 1 ? atomicAdd(&a.lc[lvl].pslots, nun) : 0;
+  write_entry(a, lvl, (int64_t)ebase + (int64_t)(b >> 32), (int64_t)ubase + (int64_t)(b & 0xffffffffull), pb, ent,
+              rb, deg);
+}
+
+// Run counters, per lane (summed over the wave when published).
 struct Ctr {
-  uint64_t reached = 0, rnnz = 0, dag = 0, full = 0;
+  uint64_t reached = 0, rnnz = 0, dag = 0, full = 0, newl = 0;
 };
 
 // ------------------------------------------------------------ forward unit
@@ -262,7 +285,11 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
           // a neighbour of a level-kl vertex is at distance kl-1, kl or kl+1
           // from the lane's source, so "not yet reached" is "on neither level"
           const uint64_t nb = em & ~(px | cur[xk]);
-          if (nb) claimed = atomicOr((unsigned long long*)&nxt[xk], (unsigned long long)nb) == 0ull;
+          if (nb) {
+            const uint64_t old = atomicOr((unsigned long long*)&nxt[xk], (unsigned long long)nb);
+            claimed = old == 0ull;
+            C.newl += (uint64_t)__popcll(nb & ~old);
+          }
         }
       }
       if (cnt) {
@@ -382,9 +409,71 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
     // edges of word k no source of the word can still discover
     if ((nv & EL) == EL && (ov & EL) != EL) C.full += (uint64_t)deg;
   }
-  const uint64_t pc = (uint64_t)__popcll(nbm);
-  C.reached += pc;
-  C.rnnz += pc * (uint64_t)deg;
+  if (lane == 0) {
+    const uint64_t pc = (uint64_t)__popcll(nbm);
+    C.reached += pc;
+    C.rnnz += pc * (uint64_t)deg;
+  }
+}
+
+// The same unit worked by one lane: an entry of <= 32 edges whose word has
+// a single lane l on level kl, and that lane propagates along edges.  Sparse
+// levels (a lane or so per entry, as on long-diameter graphs) put 64 such
+// units in a wave instead of one.  Sums run in edge order, as in the wave
+// form, so results are identical.
+template <bool EXT>
+__device__ __forceinline__ void lane_forward_unit(const BatchArgs& a, Stage& st, const BUnit& un, uint64_t bit,
+                                                  const uint64_t* par, const uint64_t* cur, uint64_t* nxt, int kl,
+                                                  bool count, bool td, int32_t ebn, int32_t ubn, Ctr& C) {
+  const int K = a.K;
+  const size_t B = (size_t)64 * K;
+  const int32_t* __restrict__ ci = a.ci;
+  const int32_t w = un.v, k = un.k, deg = un.deg;
+  const int l = __builtin_ctzll(bit);
+  const size_t col = 64 * (size_t)k + l;
+  uint64_t s = 0;
+  Ext x = ext_zero();
+  bool wrap = false;
+  for (int32_t e = un.beg; e < un.end; ++e) {
+    const int32_t xv = ci[e];
+    const size_t xk = (size_t)xv * K + k;
+    const uint64_t px = par[xk];
+    if (count && (px & bit)) {
+      C.dag += 1;
+      if (EXT) {
+        x = ext_add(x, Ext{a.sm[(size_t)xv * B + col], a.se[(size_t)xv * B + col]});
+      } else {
+        const uint64_t y = a.sig[(size_t)xv * B + col];
+        if (s + y < s) wrap = true;
+        s += y;
+      }
+    }
+    if (td && !((px | cur[xk]) & bit)) {
+      const uint64_t old = atomicOr((unsigned long long*)&nxt[xk], (unsigned long long)bit);
+      if (!(old & bit)) C.newl += 1;
+      if (old == 0ull) lane_append(a, st, kl + 1, ebn, ubn, bentry(xv, k));
+    }
+  }
+  if (!count) return;
+  const size_t idx = (size_t)w * B + col;
+  if (EXT) {
+    const Ext z = ext_norm(x);
+    a.sm[idx] = z.m;
+    a.se[idx] = z.e;
+  } else {
+    a.sig[idx] = s;
+    if (wrap) atomicOr(&a.lane_ovf[col], 1u);
+  }
+  if (a.keep_lv) a.lv[idx] = kl;
+  a.emask[un.e] = bit;
+  const size_t wk = (size_t)w * K + k;
+  const uint64_t EL = a.edge_lanes[k];
+  const uint64_t ov = a.vis[wk];
+  const uint64_t nv = ov | bit;
+  a.vis[wk] = nv;
+  if ((nv & EL) == EL && (ov & EL) != EL) C.full += (uint64_t)deg;
+  C.reached += 1;
+  C.rnnz += (uint64_t)deg;
 }
 
 // ----------------------------------------------------------- backward unit
@@ -483,6 +572,42 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const BUnit& u
   }
 }
 
+// The backward unit worked by one lane (entries of <= 32 edges with at most
+// one lane on level lb).
+template <bool EXT>
+__device__ __forceinline__ void lane_backward_unit(const BatchArgs& a, const BUnit& un, uint64_t om,
+                                                   const uint64_t* cmv, uint64_t* own, int lb, int depth) {
+  const int K = a.K;
+  const size_t B = (size_t)64 * K;
+  const int32_t* __restrict__ ci = a.ci;
+  double* psi = EXT ? a.sm : (double*)a.sig;
+  const int32_t w = un.v, k = un.k;
+  const size_t wk = (size_t)w * K + k;
+  own[wk] = om;
+  if (!om) return;
+  const int l = __builtin_ctzll(om);
+  const size_t col = 64 * (size_t)k + l;
+  const size_t idx = (size_t)w * B + col;
+  const int32_t ew = EXT ? a.se[idx] : 0;
+  double acc = 0.0;
+  if (lb < depth) {
+    for (int32_t e = un.beg; e < un.end; ++e) {
+      const int32_t xv = ci[e];
+      if (cmv[(size_t)xv * K + k] & om) {
+        double y = psi[(size_t)xv * B + col];
+        if (EXT) y = ldexp(y, ew - a.se[(size_t)xv * B + col]);
+        acc += y;
+      }
+    }
+  }
+  const double omw = a.omega ? (double)a.omega[w] : 0.0;
+  const double sw = EXT ? a.sm[idx] : (double)a.sig[idx];
+  const double delta = sw * acc;
+  psi[idx] = (1.0 + delta + omw) / sw;
+  if (a.delta_out) a.delta_out[col * a.n + w] = delta;
+  a.pair_bc[(size_t)a.lane_pair[col] * a.n + w] += a.lane_w[col] * (delta + omw);
+}
+
 // ------------------------------------------------------------- kernel
 
 template <bool EXT>
@@ -507,6 +632,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
   if (threadIdx.x == 0) {
     st.n = 0;
     st.full = 0;
+    st.newl = 0;
     st.ctr[0] = st.ctr[1] = st.ctr[2] = 0;
   }
   __syncthreads();
@@ -525,12 +651,16 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
         else a.sig[(size_t)s * B + j] = 1ull;
         atomicOr((unsigned long long*)&a.vis[(size_t)s * K + (j >> 6)], (unsigned long long)bit);
         claimed = atomicOr((unsigned long long*)&a.fm[(size_t)s * K + (j >> 6)], (unsigned long long)bit) == 0ull;
+        C.newl += 1;
         ent = bentry(s, j >> 6);
         atomicAdd(&st.ctr[0], 1ull);
         atomicAdd(&st.ctr[1], (unsigned long long)(rp[s + 1] - rp[s]));
       }
     }
     stage_append(a, st, 0, 0, 0, claimed, ent);
+    const uint64_t nl0 = wave_sum_u64(C.newl);
+    if (lane == 0 && nl0) atomicAdd(&st.newl, (unsigned long long)nl0);
+    C.newl = 0;
     stage_flush(a, st, 0, 0, 0);
   }
   if (tid == 0) { a.qoff[0] = 0; a.uoff[0] = 0; }
@@ -564,15 +694,31 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
       if (kl + 2 < a.cap_levels) a.lc[kl + 2] = LevelCtr{0ull, 0, 0, 0ull, 0, 0};
     }
     ++levels;
-    if (kl >= 1 || !bu) {
-      // the next unit's record is fetched while this one is worked on
-      BUnit nx{};
-      if (gw < nu) nx = a.U[ubase + gw];
-      for (int64_t i = gw; i < nu; i += nw) {
-        const BUnit un = nx;
-        if (i + nw < nu) nx = a.U[ubase + i + nw];
-        forward_unit<EXT>(a, st, un, par, cur, nxt, kl, kl >= 1, !bu, ebn, ubn, C);
+    // sparse levels (fewer than two lanes per entry): one unit per lane for
+    // the entries with a single edge lane, a wave per unit for the others
+    const bool sparse = ldr64(&a.lc[kl].lanes) < 2ull * (uint64_t)ne;
+    if ((kl >= 1 || !bu) && sparse) {
+      for (int64_t first = gw; first < nu; first += nw * kWave) {
+        const int64_t i = first + nw * lane;  // the wave's units: first, first + nw, ...
+        bool dense = false;
+        if (i < nu) {
+          const BUnit un = a.U[ubase + i];
+          const uint64_t nbm = cur[(size_t)un.v * K + un.k];
+          if (un.deg <= kLaneMaxDeg && __popcll(nbm) == 1 && (nbm & a.edge_lanes[un.k]) != 0)
+            lane_forward_unit<EXT>(a, st, un, nbm, par, cur, nxt, kl, kl >= 1, !bu, ebn, ubn, C);
+          else
+            dense = true;
+        }
+        uint64_t dm = ballot(dense);
+        while (dm) {
+          const int j = __builtin_ctzll(dm);
+          dm &= dm - 1;
+          forward_unit<EXT>(a, st, a.U[ubase + first + nw * j], par, cur, nxt, kl, kl >= 1, !bu, ebn, ubn, C);
+        }
       }
+    } else if (kl >= 1 || !bu) {
+      for (int64_t i = gw; i < nu; i += nw)
+        forward_unit<EXT>(a, st, a.U[ubase + i], par, cur, nxt, kl, kl >= 1, !bu, ebn, ubn, C);
     }
     if (bu) {
       ++bu_levels;
@@ -593,7 +739,11 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
         for (int32_t off = beg + lane; off < end; off += kWave) orr |= cur[(size_t)ci[off] * K + k];
         const uint64_t nb = wave_or_u64(orr) & EL & ~vk;
         bool claimed = false;
-        if (nb && lane == 0) claimed = atomicOr((unsigned long long*)&nxt[wk], (unsigned long long)nb) == 0ull;
+        if (nb && lane == 0) {
+          const uint64_t old = atomicOr((unsigned long long*)&nxt[wk], (unsigned long long)nb);
+          claimed = old == 0ull;
+          C.newl += (uint64_t)__popcll(nb & ~old);
+        }
         stage_append(a, st, nl, ebn, ubn, claimed, bentry(w, k));
       }
     }
@@ -611,7 +761,11 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
         if (pa >= 0) mine = ((((ck >> pa) | (ck >> pb)) & 1ull) != 0) && (((reached >> lane) & 1ull) == 0);
         const uint64_t nb = ballot(mine);
         bool claimed = false;
-        if (nb && lane == 0) claimed = atomicOr((unsigned long long*)&nxt[vk], (unsigned long long)nb) == 0ull;
+        if (nb && lane == 0) {
+          const uint64_t old = atomicOr((unsigned long long*)&nxt[vk], (unsigned long long)nb);
+          claimed = old == 0ull;
+          C.newl += (uint64_t)__popcll(nb & ~old);
+        }
         stage_append(a, st, nl, ebn, ubn, claimed, bentry(v, k));
       }
     }
@@ -622,8 +776,13 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
         clr[(size_t)(uint32_t)ent * K + (ent >> 32)] = 0;
       }
     }
-    if (lane == 0 && C.full) atomicAdd(&st.full, (unsigned long long)C.full);
-    C.full = 0;
+    {
+      const uint64_t fs = wave_sum_u64(C.full), ls = wave_sum_u64(C.newl);
+      if (lane == 0 && fs) atomicAdd(&st.full, (unsigned long long)fs);
+      if (lane == 0 && ls) atomicAdd(&st.newl, (unsigned long long)ls);
+      C.full = 0;
+      C.newl = 0;
+    }
     stage_flush(a, st, nl, ebn, ubn);
     grid_barrier(a.bar);
     eprev2 = eprev;
@@ -636,10 +795,10 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
 
   // ---- forward counters (workgroup first) and component sizes
   {
-    const uint64_t dag = wave_sum_u64(C.dag);  // per lane; the other counters are uniform
+    const uint64_t reached = wave_sum_u64(C.reached), rnnz = wave_sum_u64(C.rnnz), dag = wave_sum_u64(C.dag);
     if (lane == 0) {
-      if (C.reached) atomicAdd(&st.ctr[0], (unsigned long long)C.reached);
-      if (C.rnnz) atomicAdd(&st.ctr[1], (unsigned long long)C.rnnz);
+      if (reached) atomicAdd(&st.ctr[0], (unsigned long long)reached);
+      if (rnnz) atomicAdd(&st.ctr[1], (unsigned long long)rnnz);
       if (dag) atomicAdd(&st.ctr[2], (unsigned long long)dag);
     }
   }
@@ -691,12 +850,29 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
       uint64_t* own = F(lb);
       uint64_t* clr = F(lb + 2);
       const int32_t ub = a.uoff[lb], ue = a.uoff[lb + 1];
-      BUnit nx{};
-      if (gw < ue - ub) nx = a.U[ub + gw];
-      for (int64_t i = gw; i < ue - ub; i += nw) {
-        const BUnit un = nx;
-        if (i + nw < ue - ub) nx = a.U[ub + i + nw];
-        backward_unit<EXT>(a, un, cmv, own, lb, depth, st);
+      const int64_t nub = ue - ub;
+      if (ldr64(&a.lc[lb].lanes) < 2ull * (uint64_t)(a.qoff[lb + 1] - a.qoff[lb])) {
+        // sparse level: one unit per lane where the word has at most one lane here
+        for (int64_t first = gw; first < nub; first += nw * kWave) {
+          const int64_t i = first + nw * lane;
+          bool dense = false;
+          if (i < nub) {
+            const BUnit un = a.U[ub + i];
+            const uint64_t om = a.emask[un.e] & ~st.sX[un.k];
+            if (un.deg <= kLaneMaxDeg && __popcll(om) <= 1)
+              lane_backward_unit<EXT>(a, un, om, cmv, own, lb, depth);
+            else
+              dense = true;
+          }
+          uint64_t dm = ballot(dense);
+          while (dm) {
+            const int j = __builtin_ctzll(dm);
+            dm &= dm - 1;
+            backward_unit<EXT>(a, a.U[ub + first + nw * j], cmv, own, lb, depth, st);
+          }
+        }
+      } else {
+        for (int64_t i = gw; i < nub; i += nw) backward_unit<EXT>(a, a.U[ub + i], cmv, own, lb, depth, st);
       }
       // level lb+2 masks are no longer read
       if (lb + 2 <= depth) {

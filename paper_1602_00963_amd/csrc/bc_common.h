@@ -109,6 +109,7 @@ struct LevelCtr {
   unsigned long long fedges;  // sum of degrees of the appended entries
   int32_t err;        // capacity errors raised while this level's list was built
   int32_t pad;
+  unsigned long long lanes;  // (vertex, source) pairs discovered on this level (batched kernel)
 };
 // Every workgroup reads a level's counters only after the barrier that ends
 // the phase building that level, so all of them take the same decisions.
