@@ -434,24 +434,58 @@ __device__ __forceinline__ void lane_forward_unit(const BatchArgs& a, Stage& st,
   uint64_t s = 0;
   Ext x = ext_zero();
   bool wrap = false;
-  for (int32_t e = un.beg; e < un.end; ++e) {
-    const int32_t xv = ci[e];
-    const size_t xk = (size_t)xv * K + k;
-    const uint64_t px = par[xk];
-    if (count && (px & bit)) {
-      C.dag += 1;
-      if (EXT) {
-        x = ext_add(x, Ext{a.sm[(size_t)xv * B + col], a.se[(size_t)xv * B + col]});
-      } else {
-        const uint64_t y = a.sig[(size_t)xv * B + col];
-        if (s + y < s) wrap = true;
-        s += y;
+  // four edges at a time: their neighbours, masks and counts are in flight together
+  constexpr int Q4 = 4;
+  for (int32_t e0 = un.beg; e0 < un.end; e0 += Q4) {
+    int32_t xv[Q4];
+    uint64_t px[Q4], cx[Q4];
+#pragma unroll
+    for (int j = 0; j < Q4; ++j) xv[j] = e0 + j < un.end ? ci[e0 + j] : -1;
+#pragma unroll
+    for (int j = 0; j < Q4; ++j) {
+      px[j] = 0;
+      cx[j] = 0;
+      if (xv[j] >= 0) {
+        const size_t xk = (size_t)xv[j] * K + k;
+        px[j] = par[xk];
+        if (td) cx[j] = cur[xk];
       }
     }
-    if (td && !((px | cur[xk]) & bit)) {
-      const uint64_t old = atomicOr((unsigned long long*)&nxt[xk], (unsigned long long)bit);
-      if (!(old & bit)) C.newl += 1;
-      if (old == 0ull) lane_append(a, st, kl + 1, ebn, ubn, bentry(xv, k));
+    if (count) {
+      if (EXT) {
+        Ext ys[Q4];
+#pragma unroll
+        for (int j = 0; j < Q4; ++j) {
+          ys[j] = ext_zero();
+          if (px[j] & bit) ys[j] = Ext{a.sm[(size_t)xv[j] * B + col], a.se[(size_t)xv[j] * B + col]};
+        }
+#pragma unroll
+        for (int j = 0; j < Q4; ++j)
+          if (px[j] & bit) { x = ext_add(x, ys[j]); C.dag += 1; }
+      } else {
+        uint64_t ys[Q4];
+#pragma unroll
+        for (int j = 0; j < Q4; ++j) ys[j] = (px[j] & bit) ? a.sig[(size_t)xv[j] * B + col] : 0ull;
+#pragma unroll
+        for (int j = 0; j < Q4; ++j) {
+          if (px[j] & bit) {
+            if (s + ys[j] < s) wrap = true;
+            s += ys[j];
+            C.dag += 1;
+          }
+        }
+      }
+    }
+    if (td) {
+#pragma unroll
+      for (int j = 0; j < Q4; ++j) {
+        if (xv[j] >= 0 && !((px[j] | cx[j]) & bit)) {
+          const size_t xk = (size_t)xv[j] * K + k;
+          const uint64_t old = atomicOr((unsigned long long*)&nxt[xk], (unsigned long long)bit);
+          if (!(old & bit)) C.newl += 1;
+          if (old == 0ull) lane_append(a, st, kl + 1, ebn, ubn, bentry(xv[j], k));
+        }
+      }
     }
   }
   if (!count) return;
@@ -591,13 +625,26 @@ __device__ __forceinline__ void lane_backward_unit(const BatchArgs& a, const BUn
   const int32_t ew = EXT ? a.se[idx] : 0;
   double acc = 0.0;
   if (lb < depth) {
-    for (int32_t e = un.beg; e < un.end; ++e) {
-      const int32_t xv = ci[e];
-      if (cmv[(size_t)xv * K + k] & om) {
-        double y = psi[(size_t)xv * B + col];
-        if (EXT) y = ldexp(y, ew - a.se[(size_t)xv * B + col]);
-        acc += y;
+    constexpr int Q4 = 4;
+    for (int32_t e0 = un.beg; e0 < un.end; e0 += Q4) {
+      int32_t xv[Q4];
+      bool on[Q4];
+      double ys[Q4];
+#pragma unroll
+      for (int j = 0; j < Q4; ++j) xv[j] = e0 + j < un.end ? ci[e0 + j] : -1;
+#pragma unroll
+      for (int j = 0; j < Q4; ++j) on[j] = xv[j] >= 0 && (cmv[(size_t)xv[j] * K + k] & om) != 0;
+#pragma unroll
+      for (int j = 0; j < Q4; ++j) {
+        ys[j] = 0.0;
+        if (on[j]) {
+          ys[j] = psi[(size_t)xv[j] * B + col];
+          if (EXT) ys[j] = ldexp(ys[j], ew - a.se[(size_t)xv[j] * B + col]);
+        }
       }
+#pragma unroll
+      for (int j = 0; j < Q4; ++j)
+        if (on[j]) acc += ys[j];
     }
   }
   const double omw = a.omega ? (double)a.omega[w] : 0.0;
