@@ -972,16 +972,33 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
   bc_status s = BC_OK;
   std::vector<Group> rest;
   if (r.mode == BC_MODE_BATCHED && r.sigma_mode == BC_SIGMA_AUTO && triples.empty() &&
-      groups.size() > (size_t)(4 * r.B)) {
-    // probe: one batch in exact form; if most of its sources wrap (long
-    // diameters), the other batches go straight to the extended form
-    std::vector<Group> head(groups.begin(), groups.begin() + r.B);
-    rest.assign(groups.begin() + r.B, groups.end());
-    s = run_groups(g, r, false, tg, head, {}, workspace, ws_bytes, st, slots, nslots, &co);
+      groups.size() > (size_t)r.B) {
+    // probe: one word of sources in exact form (lists at their worst-case
+    // size); if most of them wrap (long diameters), the other batches go
+    // straight to the extended form, and - when the library owns the
+    // workspace - with worst-case lists and batches narrow enough for them,
+    // since on such graphs a vertex sits on a different level for nearly
+    // every source
+    Resolved rp = r, rr = r;
+    rp.B = 64;
+    rp.K = 1;
+    rp.cap_factor = 64;
+    std::vector<Group> head(groups.begin(), groups.begin() + 64);
+    rest.assign(groups.begin() + 64, groups.end());
+    s = run_groups(g, workspace ? r : rp, false, tg, head, {}, workspace, ws_bytes, st, slots, nslots, &co);
     if (s != BC_OK) return s;
-    if (2 * co.ovf.size() > head.size()) ext0 = true;
+    if (2 * co.ovf.size() > head.size()) {
+      ext0 = true;
+      if (!workspace) {
+        rr.cap_factor = 64;
+        while (rr.B > 64 && (int64_t)g->n * rr.B + 1024 > (int64_t)INT32_MAX / 2) {
+          rr.B /= 2;
+          rr.K = rr.B / 64;
+        }
+      }
+    }
     CallOut c2;
-    s = run_groups(g, r, ext0, tg, rest, {}, workspace, ws_bytes, st, slots, nslots, &c2);
+    s = run_groups(g, rr, ext0, tg, rest, {}, workspace, ws_bytes, st, slots, nslots, &c2);
     if (s != BC_OK) return s;
     co.merge(c2);
     co.ovf.insert(co.ovf.end(), c2.ovf.begin(), c2.ovf.end());
