@@ -279,14 +279,35 @@ def test_autotune_leaves_scores_and_results_unchanged(bcm, ctx):
     G.close()
 
 
-def test_long_diameter_lattice_auto_mode(bcm, ctx):
+@pytest.mark.parametrize("batch", [64, 256])
+def test_long_diameter_lattice_auto_mode(bcm, ctx, batch):
     """A 96 x 96 road-like lattice, every source, automatic count form: about
-    90% of sources wrap uint64, so after the probe batch the rest run in
-    extended form; scores match the oracle (long-double reruns)."""
+    90% of sources wrap uint64, so after the probe word the rest run in
+    extended form with worst-case level lists; most levels carry about one
+    lane per (vertex, word), so the one-lane-per-unit path does most of the
+    work; scores match the oracle (long-double reruns)."""
     g = gg.road_grid(96, 96, 0.05, 0.01, 9)
-    say("case lattice auto")
+    say("case lattice auto", batch)
     ref, ovf = oracle.bc(g, nthreads=8)
     assert ovf.mean() > 0.5
-    got, st = run_bc(bcm, ctx, g, mode="batched", batch=64)
+    got, st = run_bc(bcm, ctx, g, mode="batched", batch=batch)
     assert st["overflowed"] > 0
-    assert_close(got, ref, what="lattice auto")
+    assert_close(got, ref, what=f"lattice auto b{batch}")
+
+
+def test_sparse_sources_on_lattice_exact(bcm, ctx):
+    """Few sources far apart on a lattice small enough for exact counts:
+    nearly every (vertex, word) has a single lane, so both sweeps run one
+    unit per lane; d and sigma bit-exact, delta and scores within 1e-9."""
+    g = gg.road_grid(30, 30, 0.05, 0.01, 4)
+    S = gg.sample(g.non_isolated(), 48, 12)
+    say("case sparse lattice")
+    tr = bcm.Graph(ctx, g).trace(S, mode="batched", batch=64)
+    for i, s in enumerate(S):
+        o = oracle.source(g, s)
+        assert not o["overflow"] and not tr["overflow"][i]
+        assert np.array_equal(tr["d"][i], o["d"]), f"d differs for source {s}"
+        assert np.array_equal(tr["sigma"][i], o["sigma"]), f"sigma differs for source {s}"
+    ref, _ = oracle.bc(g, S)
+    got, _ = run_bc(bcm, ctx, g, S, mode="batched", batch=64)
+    assert_close(got, ref, what="sparse lattice")
