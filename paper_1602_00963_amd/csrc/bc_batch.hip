@@ -39,6 +39,12 @@
 // Entries spanning several units combine per-unit partial sums in unit
 // order (the last arriving wave does it), so results do not depend on
 // scheduling.
+// Sparse levels (fewer than two lanes per entry on average, the long tail
+// of a deep graph): a unit whose entry has one edge lane and at most 32
+// edges is walked by a single lane, 64 such units per wave, both sweeps;
+// the others keep the wave-per-unit form.  The forward sweep records each
+// entry's lane mask, which the backward sweep reads instead of per-lane
+// levels.
 #include "bc_common.h"
 #include "bc_kernels.h"
 
