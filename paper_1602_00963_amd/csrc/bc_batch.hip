@@ -80,6 +80,7 @@ struct Stage {
   uint64_t wu[kWavesPB], wp[kWavesPB], wd[kWavesPB];
   uint64_t sX[kMaxWords];
   unsigned long long ctr[3];
+  int32_t fclaim[2], bclaim[2];  // unit claims of the forward phases and backward levels, by parity
 };
 
 __device__ __forceinline__ void raise_b(const BatchArgs& a, int lvl, int32_t code) {
@@ -242,6 +243,16 @@ __device__ __forceinline__ void lane_append(const BatchArgs& a, Stage& st, int l
   const int64_t pb = nun > 1 ? atomicAdd(&a.lc[lvl].pslots, nun) : 0;
   write_entry(a, lvl, (int64_t)ebase + (int64_t)(b >> 32), (int64_t)ubase + (int64_t)(b & 0xffffffffull), pb, ent,
               rb, deg);
+}
+
+// Units of a phase are dealt to workgroups by a fixed stride (workgroup b
+// gets units b, b + G, b + 2 G, ... for a grid of G) and claimed inside the
+// workgroup one at a time from an LDS counter, so heavy and light units
+// spread over the workgroup's waves as they finish.
+__device__ __forceinline__ int64_t wg_claim(int32_t* ctr) {
+  int32_t v = 0;
+  if (lane_id() == 0) v = atomicAdd(ctr, 1);
+  return (int64_t)blockIdx.x + (int64_t)gridDim.x * (int64_t)__builtin_amdgcn_readfirstlane(v);
 }
 
 // Run counters, per lane (summed over the wave when published).
@@ -687,6 +698,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     st.full = 0;
     st.newl = 0;
     st.ctr[0] = st.ctr[1] = st.ctr[2] = 0;
+    st.fclaim[0] = st.fclaim[1] = st.bclaim[0] = st.bclaim[1] = 0;
   }
   __syncthreads();
 
@@ -741,6 +753,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     const double fe = (double)ldr64(&a.lc[kl].fedges);
     const double unvisited = (double)a.nnz * kact - (double)ldr64(a.fulledges);
     const bool bu = kl > 0 && a.alpha > 0.0 && fe * a.alpha > unvisited;
+    if (threadIdx.x == 0) st.fclaim[nl & 1] = 0;  // phase kl+1's counter; kl-1 used it before the barrier
     if (tid == 0) {
       a.qoff[nl] = ebn;
       a.uoff[nl] = ubn;
@@ -770,7 +783,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
         }
       }
     } else if (kl >= 1 || !bu) {
-      for (int64_t i = gw; i < nu; i += nw)
+      for (int64_t i = wg_claim(&st.fclaim[kl & 1]); i < nu; i = wg_claim(&st.fclaim[kl & 1]))
         forward_unit<EXT>(a, st, a.U[ubase + i], par, cur, nxt, kl, kl >= 1, !bu, ebn, ubn, C);
     }
     if (bu) {
@@ -904,6 +917,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
       uint64_t* clr = F(lb + 2);
       const int32_t ub = a.uoff[lb], ue = a.uoff[lb + 1];
       const int64_t nub = ue - ub;
+      if (threadIdx.x == 0) st.bclaim[(lb - 1) & 1] = 0;  // the next level's counter
       if (ldr64(&a.lc[lb].lanes) < 2ull * (uint64_t)(a.qoff[lb + 1] - a.qoff[lb])) {
         // sparse level: one unit per lane where the word has at most one lane here
         for (int64_t first = gw; first < nub; first += nw * kWave) {
@@ -925,7 +939,8 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
           }
         }
       } else {
-        for (int64_t i = gw; i < nub; i += nw) backward_unit<EXT>(a, a.U[ub + i], cmv, own, lb, depth, st);
+        for (int64_t i = wg_claim(&st.bclaim[lb & 1]); i < nub; i = wg_claim(&st.bclaim[lb & 1]))
+          backward_unit<EXT>(a, a.U[ub + i], cmv, own, lb, depth, st);
       }
       // level lb+2 masks are no longer read
       if (lb + 2 <= depth) {
