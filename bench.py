@@ -7,7 +7,7 @@ GTEPS (sources x undirected edges / s), the roofline of the dominant kernel,
 the one-source-per-launch form on a source sample, and the CPU oracle timed
 on the host on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config rmat16]
 """
 from __future__ import annotations
 
@@ -32,18 +32,18 @@ def log(*a):
 
 def workload(name: str, sources_arg: int):
     import graphgen as gg
-    if name == "c1":
-        g, wl, prune = gg.config_c1(), "rmat10_ef16_all_sources", False
-    elif name == "c2":
-        g, wl, prune = gg.config_c2(), "rmat16_ef16_all_sources", False
-    elif name == "c3":
-        g, wl, prune = gg.config_c3(), "rmat20_ef16_plus30pct_pendants_pruned", True
-    elif name == "c4":
-        g, wl, prune = gg.config_c4(), "grid2048_roadlike_8192_sources", False
+    if name == "rmat10":
+        g, wl, prune = gg.workload_rmat10(), "rmat10_ef16_all_sources", False
+    elif name == "rmat16":
+        g, wl, prune = gg.workload_rmat16(), "rmat16_ef16_all_sources", False
+    elif name == "rmat20p":
+        g, wl, prune = gg.workload_rmat20_pendants(), "rmat20_ef16_plus30pct_pendants_pruned", True
+    elif name == "grid2048":
+        g, wl, prune = gg.workload_roadlike_grid(), "grid2048_roadlike_8192_sources", False
         if sources_arg <= 0:
             sources_arg = 8192
     else:
-        raise SystemExit(f"unknown config {name}")
+        raise SystemExit(f"unknown workload {name} (rmat10, rmat16, rmat20p, grid2048)")
     src = None
     if sources_arg > 0:
         src = gg.sample(g.non_isolated(), min(sources_arg, len(g.non_isolated())), 44)
@@ -268,14 +268,23 @@ def cpu_baseline(g, m: int, budget_s: float, seed: int = 91):
                       f"per source, static split over {cores} threads; {dt:.1f} s"}
 
 
+# Batch widths measured fastest on MI355X (sweep of 128..1024 sources per
+# launch): the scale-16 all-sources run gains from 512, the scale-20 graph
+# (ten times the vertices per level) does best at 256.
+BEST_BATCH = {"rmat16": 512}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="rmat16",
+                    help="workload: rmat10, rmat16 (default), rmat20p (with pendants, pruned), grid2048")
     ap.add_argument("--sources", type=int, default=0, help="sample this many sources (0 = all)")
-    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--batch", type=int, default=0,
+                    help="sources per launch (0 = the width measured fastest for the workload: "
+                         "512 on the scale-16 graph, 256 on the others)")
     ap.add_argument("--mode", default="batched")
     ap.add_argument("--alpha", type=float, default=0.0)
     ap.add_argument("--grid-per-cu", type=int, default=0)
@@ -318,6 +327,8 @@ def main():
     import paper_1602_00963_amd as bcm
 
     g, wl, prune, sources = workload(args.config, args.sources)
+    if args.batch == 0:
+        args.batch = BEST_BATCH.get(args.config, 256)
     n, nnz, m = g.n, g.nnz, g.m
     log(f"workload {wl}: n={n} m={m}")
     ctx = bcm.Context(0)

@@ -283,24 +283,24 @@ def add_pendants(g: Graph, hubs) -> Graph:
                       name=g.name + "_pend")
 
 
-# ------------------------------------------------------------- benchmark configs
+# ------------------------------------------------------------- benchmark workloads
 
-def config_c1() -> Graph:
+def workload_rmat10() -> Graph:
     """R-MAT scale 10, edge factor 16, seed 1."""
     return rmat(10, 16, 1)
 
 
-def config_c2() -> Graph:
+def workload_rmat16() -> Graph:
     """R-MAT scale 16, edge factor 16, seed 2."""
     return rmat(16, 16, 2)
 
 
-def config_c3(scale: int = 20) -> Graph:
+def workload_rmat20_pendants(scale: int = 20) -> Graph:
     """R-MAT (scale, EF 16, seed 3) plus 30% extra pendant vertices (seed 33)."""
     return rmat_with_pendants(scale, 16, 3, 0.3, pend_seed=33)
 
 
-def config_c4(R: int = 2048, C: int = 2048) -> Graph:
+def workload_roadlike_grid(R: int = 2048, C: int = 2048) -> Graph:
     """Road-like lattice: 5% lattice edges removed, 1% local diagonals, seed 4."""
     return road_grid(R, C, 0.05, 0.01, 4)
 

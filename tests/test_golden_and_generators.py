@@ -61,7 +61,7 @@ def test_generators_deterministic_and_valid():
     assert np.array_equal(a.row_ptr, b.row_ptr) and np.array_equal(a.col_idx, b.col_idx)
     c = gg.rmat(12, 16, 10)
     assert not np.array_equal(a.col_idx[:100], c.col_idx[:100])
-    for g in [a, gg.config_c1(), gg.rmat_with_pendants(12, 16, 3, 0.3, 33), gg.road_grid(64, 48, 0.05, 0.01, 4),
+    for g in [a, gg.workload_rmat10(), gg.rmat_with_pendants(12, 16, 3, 0.3, 33), gg.road_grid(64, 48, 0.05, 0.01, 4),
               gg.hypercube(5), gg.layered_chain(4, 3), gg.random_tree(30, 1), gg.full_grid(5, 7)]:
         csr_ok(g)
 

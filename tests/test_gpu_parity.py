@@ -61,7 +61,7 @@ MODE_IDS = ["plain", "b64", "b128", "b256", "b192", "b1024"]
 @pytest.mark.parametrize("opts", MODES, ids=MODE_IDS)
 def test_rmat_scale10_all_sources(bcm, ctx, opts):
     """The small R-MAT workload (scale 10, EF 16): every source."""
-    g = gg.config_c1()
+    g = gg.workload_rmat10()
     say("case rmat10 all sources", opts)
     ref, _ = oracle.bc(g, nthreads=4)
     got, st = run_bc(bcm, ctx, g, **opts)
@@ -240,7 +240,7 @@ def test_run_stats_match_oracle_counts(bcm, ctx):
 def test_rmat_scale16_sampled_sources(bcm, ctx):
     """The scale-16 workload at full size: 256 sampled sources through the
     batched launch shape used by the benchmark, and 32 through plain."""
-    g = gg.config_c2()
+    g = gg.workload_rmat16()
     S = gg.sample(g.non_isolated(), 256, 11)
     say("case rmat16 sampled")
     ref, _ = oracle.bc(g, S, nthreads=8)

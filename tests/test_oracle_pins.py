@@ -73,7 +73,7 @@ def test_bellman_matches_exact_enumeration():
 
 def test_r_mat_scale10_three_ways():
     """The small R-MAT workload: Brandes vs the O(n^3) Bellman method vs networkx."""
-    g = gg.config_c1()
+    g = gg.workload_rmat10()
     raw, ovf = oracle.bc(g)
     assert not ovf.any()
     assert_close(raw, oracle.bellman(g))
