@@ -361,21 +361,21 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
   if (deg > CHB) {
     const int32_t nunits = units_of<CHB>(deg);
     const size_t pi = (size_t)(un.pb + c) * 64 + lane;
-    if (EXT) { a.part_m[pi] = x.m; a.part_e[pi] = x.e; }
-    else { a.part_m[pi] = __longlong_as_double((long long)s); a.part_e[pi] = wrap ? 1 : 0; }
-    fence_release();
+    if (EXT) { part_store(&a.part_m[pi], x.m); part_store(&a.part_e[pi], x.e); }
+    else { part_store(&a.part_m[pi], __longlong_as_double((long long)s)); part_store(&a.part_e[pi], wrap ? 1 : 0); }
+    part_stores_done();
     int32_t prev = 0;
     if (lane == 0) prev = atomicAdd(&a.arrive[un.e], 1);
     prev = __shfl(prev, 0, kWave);
     if (prev != nunits - 1) return;
-    fence_acquire();
+    part_loads_after();
     s = 0;
     x = ext_zero();
     wrap = false;
     for (int32_t cc = 0; cc < nunits; ++cc) {
       const size_t pc = (size_t)(un.pb + cc) * 64 + lane;
-      const double pm = __hip_atomic_load(&a.part_m[pc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int32_t pe = __hip_atomic_load(&a.part_e[pc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const double pm = part_load(&a.part_m[pc]);
+      const int32_t pe = part_load(&a.part_e[pc]);
       if (EXT) {
         x = ext_add(x, Ext{pm, pe});
       } else {
@@ -591,17 +591,15 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const BUnit& u
   }
   if (un.deg > CHB) {
     const int32_t nunits = units_of<CHB>(un.deg);
-    a.part_m[(size_t)(un.pb + c) * 64 + lane] = acc;
-    fence_release();
+    part_store(&a.part_m[(size_t)(un.pb + c) * 64 + lane], acc);
+    part_stores_done();
     int32_t prev = 0;
     if (lane == 0) prev = atomicAdd(&a.arrive[un.e], 1);
     prev = __shfl(prev, 0, kWave);
     if (prev != 2 * nunits - 1) return;  // the forward counting phase took the first nunits arrivals
-    fence_acquire();
+    part_loads_after();
     acc = 0.0;
-    for (int32_t cc = 0; cc < nunits; ++cc)
-      acc += __hip_atomic_load(&a.part_m[(size_t)(un.pb + cc) * 64 + lane], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+    for (int32_t cc = 0; cc < nunits; ++cc) acc += part_load(&a.part_m[(size_t)(un.pb + cc) * 64 + lane]);
   }
   if (!om) return;
   const double omw = a.omega ? (double)a.omega[w] : 0.0;

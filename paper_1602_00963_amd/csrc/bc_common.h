@@ -194,8 +194,26 @@ __device__ __forceinline__ void raise_err(const Lists& L, int lvl, int32_t code)
   atomicOr(L.err, code);
 }
 
-__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+// Partial sums of a split entry pass from the waves that work its units to
+// the last one to arrive, possibly on another XCD.  They are written and
+// read with device-scope accesses, which go through each XCD's L2 to the
+// device's coherence point, and a wave waits for its partial stores to
+// complete before it counts its arrival.  No agent-scope fence is needed:
+// on this chip a release fence writes back the XCD's whole L2 and an
+// acquire fence invalidates it, which once per split unit cost about half
+// of the batched kernel's time.
+template <typename T>
+__device__ __forceinline__ void part_store(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T part_load(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// The wave's partial stores have completed (before its arrival is counted).
+__device__ __forceinline__ void part_stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Keeps the compiler from moving partial loads above the arrival count.
+__device__ __forceinline__ void part_loads_after() { asm volatile("" ::: "memory"); }
 
 // Wave-aggregated append of the lanes with `want` to level `lvl`'s list:
 // one 64-bit atomic per wave reserves both the entry positions and the

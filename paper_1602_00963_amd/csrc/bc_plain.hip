@@ -232,16 +232,16 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
             a.sm[w] = z.m; a.se[w] = z.e;
           } else {
             const int32_t nunits = units_of<CHP>(rp[w + 1] - rp[w]);
-            a.part_m[un.pb + un.c] = s.m;
-            a.part_e[un.pb + un.c] = s.e;
-            fence_release();
+            part_store(&a.part_m[un.pb + un.c], s.m);
+            part_store(&a.part_e[un.pb + un.c], s.e);
+            part_stores_done();
             const int32_t old = atomicAdd(&a.arrive[un.mi], 1);
             if (old == nunits - 1) {
-              fence_acquire();
+              part_loads_after();
               Ext tot = ext_zero();
               for (int32_t c = 0; c < nunits; ++c) {
-                const double pm = __hip_atomic_load(&a.part_m[un.pb + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const int32_t pe = __hip_atomic_load(&a.part_e[un.pb + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const double pm = part_load(&a.part_m[un.pb + c]);
+                const int32_t pe = part_load(&a.part_e[un.pb + c]);
                 tot = ext_add(tot, Ext{pm, pe});
               }
               const Ext z = ext_norm(tot);
@@ -299,14 +299,13 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
           } else {
             const int32_t nunits = units_of<CHP>(rp[w + 1] - rp[w]);
             const int32_t target = (EXT ? 2 : 1) * nunits - 1;
-            a.part_m[un.pb + un.c] = s;
-            fence_release();
+            part_store(&a.part_m[un.pb + un.c], s);
+            part_stores_done();
             const int32_t old = atomicAdd(&a.arrive[un.mi], 1);
             if (old == target) {
-              fence_acquire();
+              part_loads_after();
               double tot = 0.0;
-              for (int32_t c = 0; c < nunits; ++c)
-                tot += __hip_atomic_load(&a.part_m[un.pb + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              for (int32_t c = 0; c < nunits; ++c) tot += part_load(&a.part_m[un.pb + c]);
               plain_finalize<EXT>(a, w, tot);
             }
           }

@@ -237,18 +237,46 @@ def test_run_stats_match_oracle_counts(bcm, ctx):
         assert rs["dag_edges"] == st[:, 2].sum()
 
 
-def test_rmat_scale16_sampled_sources(bcm, ctx):
-    """The scale-16 workload at full size: 256 sampled sources through the
-    batched launch shape used by the benchmark, and 32 through plain."""
+@pytest.mark.parametrize("batch", [256, 512])
+def test_rmat_scale16_sampled_sources(bcm, ctx, batch):
+    """The scale-16 workload at full size: 512 sampled sources through the
+    batched launch shapes (512 sources per launch is the benchmark's), and
+    32 through plain."""
     g = gg.workload_rmat16()
-    S = gg.sample(g.non_isolated(), 256, 11)
-    say("case rmat16 sampled")
+    S = gg.sample(g.non_isolated(), 512, 11)
+    say("case rmat16 sampled", batch)
     ref, _ = oracle.bc(g, S, nthreads=8)
-    got, _ = run_bc(bcm, ctx, g, S, mode="batched", batch=256)
-    assert_close(got, ref, what="rmat16 batched")
-    ref2, _ = oracle.bc(g, S[:32], nthreads=8)
-    got2, _ = run_bc(bcm, ctx, g, S[:32], mode="plain")
-    assert_close(got2, ref2, what="rmat16 plain")
+    got, _ = run_bc(bcm, ctx, g, S, mode="batched", batch=batch)
+    assert_close(got, ref, what=f"rmat16 batched b{batch}")
+    if batch == 256:
+        ref2, _ = oracle.bc(g, S[:32], nthreads=8)
+        got2, _ = run_bc(bcm, ctx, g, S[:32], mode="plain")
+        assert_close(got2, ref2, what="rmat16 plain")
+
+
+def test_rmat_scale16_hub_sources_traced(bcm, ctx):
+    """Per-source d and sigma bit-exact at full size for sources next to the
+    highest-degree vertices: their adjacency lists span many work units, so
+    every level combines split entries (partial sums handed between waves)
+    in both sweeps; delta within 1e-9."""
+    g = gg.workload_rmat16()
+    rp = np.asarray(g.row_ptr)
+    deg = np.diff(rp)
+    hubs = np.argsort(-deg, kind="stable")[:4]
+    ci = np.asarray(g.col_idx)
+    near = np.unique(np.concatenate([ci[rp[h]:rp[h] + 16] for h in hubs] + [hubs]))
+    S = [int(v) for v in near[:64]]
+    say("case rmat16 hub trace", len(S), int(deg[hubs[0]]))
+    assert deg[hubs[0]] > 4 * 256
+    tr = bcm.Graph(ctx, g).trace(S, mode="batched", batch=512)
+    for i, s in enumerate(S):
+        o = oracle.source(g, s)
+        assert not o["overflow"] and not tr["overflow"][i]
+        assert np.array_equal(tr["d"][i], o["d"]), f"d differs for source {s}"
+        assert np.array_equal(tr["sigma"][i], o["sigma"]), f"sigma differs for source {s}"
+        dl = o["delta"].copy()
+        dl[s] = 0.0  # the source's own dependency is not part of any score
+        assert_close(tr["delta"][i], dl, what=f"delta of source {s}")
 
 
 def test_device_score_output_and_workspace(bcm, ctx):
