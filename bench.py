@@ -269,9 +269,9 @@ def cpu_baseline(g, m: int, budget_s: float, seed: int = 91):
 
 
 # Batch widths measured fastest on MI355X (sweep of 128..1024 sources per
-# launch): the scale-16 all-sources run gains from 512, the scale-20 graph
+# launch): the scale-16 all-sources run gains from 1024, the scale-20 graph
 # (ten times the vertices per level) does best at 256.
-BEST_BATCH = {"rmat16": 512}
+BEST_BATCH = {"rmat16": 1024}
 
 
 def main():
@@ -284,7 +284,7 @@ def main():
     ap.add_argument("--sources", type=int, default=0, help="sample this many sources (0 = all)")
     ap.add_argument("--batch", type=int, default=0,
                     help="sources per launch (0 = the width measured fastest for the workload: "
-                         "512 on the scale-16 graph, 256 on the others)")
+                         "1024 on the scale-16 graph, 256 on the others)")
     ap.add_argument("--mode", default="batched")
     ap.add_argument("--alpha", type=float, default=0.0)
     ap.add_argument("--grid-per-cu", type=int, default=0)

@@ -148,14 +148,20 @@ __device__ __forceinline__ void grid_barrier(GridBar* b) {
     const unsigned nx = (nb + 7u - x) / 8u;
     const unsigned ntop = nb < 8u ? nb : 8u;
     bool last = false;
-    if (__hip_atomic_fetch_add(&b->xcd[x].v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == nx - 1u) {
+    // Arrivals are relaxed: each workgroup's writes were released by the
+    // fence above.  Only the workgroups that pass an arrival on (the last
+    // of an XCD, the last overall) acquire and release again, so that the
+    // others' writes reach the waiters through them.
+    if (__hip_atomic_fetch_add(&b->xcd[x].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nx - 1u) {
       __hip_atomic_store(&b->xcd[x].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (__hip_atomic_fetch_add(&b->top.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == ntop - 1u) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      if (__hip_atomic_fetch_add(&b->top.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ntop - 1u) {
         __hip_atomic_store(&b->top.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         last = true;
       }
     }
     if (last) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __hip_atomic_store(&b->gen.v, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       while (__hip_atomic_load(&b->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
