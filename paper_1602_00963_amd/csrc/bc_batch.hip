@@ -268,7 +268,7 @@ template <bool EXT>
 __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, const BUnit& un, const uint64_t* par,
                                              const uint64_t* cur, uint64_t* nxt, int kl, bool count, bool td,
                                              int32_t ebn, int32_t ubn, Ctr& C) {
-  constexpr int G = EXT ? 8 : 16;  // neighbour rows loaded before any is consumed
+  constexpr int G = 8;  // neighbour rows loaded before any is consumed
   const int K = a.K;
   const size_t B = (size_t)64 * K;
   const int lane = lane_id();

@@ -237,13 +237,13 @@ def test_run_stats_match_oracle_counts(bcm, ctx):
         assert rs["dag_edges"] == st[:, 2].sum()
 
 
-@pytest.mark.parametrize("batch", [256, 512])
+@pytest.mark.parametrize("batch", [256, 1024])
 def test_rmat_scale16_sampled_sources(bcm, ctx, batch):
-    """The scale-16 workload at full size: 512 sampled sources through the
-    batched launch shapes (512 sources per launch is the benchmark's), and
+    """The scale-16 workload at full size: 1,024 sampled sources through the
+    batched launch shapes (1,024 sources per launch is the benchmark's), and
     32 through plain."""
     g = gg.workload_rmat16()
-    S = gg.sample(g.non_isolated(), 512, 11)
+    S = gg.sample(g.non_isolated(), 1024, 11)
     say("case rmat16 sampled", batch)
     ref, _ = oracle.bc(g, S, nthreads=8)
     got, _ = run_bc(bcm, ctx, g, S, mode="batched", batch=batch)
@@ -268,7 +268,7 @@ def test_rmat_scale16_hub_sources_traced(bcm, ctx):
     S = [int(v) for v in near[:64]]
     say("case rmat16 hub trace", len(S), int(deg[hubs[0]]))
     assert deg[hubs[0]] > 4 * 256
-    tr = bcm.Graph(ctx, g).trace(S, mode="batched", batch=512)
+    tr = bcm.Graph(ctx, g).trace(S, mode="batched", batch=1024)
     for i, s in enumerate(S):
         o = oracle.source(g, s)
         assert not o["overflow"] and not tr["overflow"][i]
