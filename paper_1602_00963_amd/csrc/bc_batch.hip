@@ -37,8 +37,11 @@
 //   into a per-(word, slot) array; after the sweep one pass folds those
 //   arrays into the slots' scores in word order.
 // Entries spanning several units combine per-unit partial sums in unit
-// order (the last arriving wave does it), so results do not depend on
-// scheduling.
+// order (the last arriving wave does it, reading the others' partials
+// through device-scope accesses rather than behind cache-wide fences), so
+// results do not depend on scheduling.  Units of dense levels are dealt to
+// workgroups by stride and claimed inside each workgroup from an LDS
+// counter, so a workgroup's waves share its heavy and light units.
 // Sparse levels (fewer than two lanes per entry on average, the long tail
 // of a deep graph): a unit whose entry has one edge lane and at most 32
 // edges is walked by a single lane, 64 such units per wave, both sweeps;
