@@ -423,11 +423,15 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
   }
   if (lane == 0) {
     a.emask[un.e] = nbm;
-    const uint64_t ov = a.vis[wk];
-    const uint64_t nv = ov | nbm;
-    a.vis[wk] = nv;
-    // edges of word k no source of the word can still discover
-    if ((nv & EL) == EL && (ov & EL) != EL) C.full += (uint64_t)deg;
+    if (a.alpha > 0.0) {
+      const uint64_t ov = a.vis[wk];
+      const uint64_t nv = ov | nbm;
+      a.vis[wk] = nv;
+      // edges of word k no source of the word can still discover (bottom-up test)
+      if ((nv & EL) == EL && (ov & EL) != EL) C.full += (uint64_t)deg;
+    } else {
+      atomicOr((unsigned long long*)&a.vis[wk], (unsigned long long)nbm);  // no round trip
+    }
   }
   if (lane == 0) {
     const uint64_t pc = (uint64_t)__popcll(nbm);
@@ -522,10 +526,14 @@ __device__ __forceinline__ void lane_forward_unit(const BatchArgs& a, Stage& st,
   a.emask[un.e] = bit;
   const size_t wk = (size_t)w * K + k;
   const uint64_t EL = a.edge_lanes[k];
-  const uint64_t ov = a.vis[wk];
-  const uint64_t nv = ov | bit;
-  a.vis[wk] = nv;
-  if ((nv & EL) == EL && (ov & EL) != EL) C.full += (uint64_t)deg;
+  if (a.alpha > 0.0) {
+    const uint64_t ov = a.vis[wk];
+    const uint64_t nv = ov | bit;
+    a.vis[wk] = nv;
+    if ((nv & EL) == EL && (ov & EL) != EL) C.full += (uint64_t)deg;
+  } else {
+    atomicOr((unsigned long long*)&a.vis[wk], (unsigned long long)bit);
+  }
   C.reached += 1;
   C.rnnz += (uint64_t)deg;
 }
@@ -619,7 +627,9 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const BUnit& u
     const int pv = __builtin_amdgcn_readlane(pr, __builtin_ctzll(rem));
     const uint64_t same = ballot(pr == pv) & rem;
     const double part = wave_sum(((same >> lane) & 1ull) ? cs : 0.0);
-    if (lane == 0) a.pair_bc[(size_t)pv * a.n + w] += part;
+    // one unit per (pair, vertex) and level: the adds land in level order;
+    // an atomic add needs no round trip before the wave moves on
+    if (lane == 0) atomicAdd(&a.pair_bc[(size_t)pv * a.n + w], part);
     rem &= ~same;
   }
 }
@@ -670,7 +680,7 @@ __device__ __forceinline__ void lane_backward_unit(const BatchArgs& a, const BUn
   const double delta = sw * acc;
   psi[idx] = (1.0 + delta + omw) / sw;
   if (a.delta_out) a.delta_out[col * a.n + w] = delta;
-  a.pair_bc[(size_t)a.lane_pair[col] * a.n + w] += a.lane_w[col] * (delta + omw);
+  atomicAdd(&a.pair_bc[(size_t)a.lane_pair[col] * a.n + w], a.lane_w[col] * (delta + omw));
 }
 
 // ------------------------------------------------------------- kernel
