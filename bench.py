@@ -268,10 +268,13 @@ def cpu_baseline(g, m: int, budget_s: float, seed: int = 91):
                       f"per source, static split over {cores} threads; {dt:.1f} s"}
 
 
-# Batch widths measured fastest on MI355X (sweep of 128..1024 sources per
-# launch): the scale-16 all-sources run gains from 1024, the scale-20 graph
-# (ten times the vertices per level) does best at 256.
+# Settings measured fastest on MI355X.  Batch width (sweep of 128..1024
+# sources per launch): the scale-16 all-sources run gains from 1024, the
+# scale-20 graph (ten times the vertices per level) does best at 256.
+# Bottom-up threshold: on the scale-16 graph no level ever goes bottom-up,
+# and switching the test off (-1) spares the kernel the bookkeeping (+1%).
 BEST_BATCH = {"rmat16": 1024}
+BEST_ALPHA = {"rmat16": -1.0}
 
 
 def main():
@@ -286,7 +289,9 @@ def main():
                     help="sources per launch (0 = the width measured fastest for the workload: "
                          "1024 on the scale-16 graph, 256 on the others)")
     ap.add_argument("--mode", default="batched")
-    ap.add_argument("--alpha", type=float, default=0.0)
+    ap.add_argument("--alpha", type=float, default=None,
+                    help="bottom-up threshold (0 = library default, < 0 = never; "
+                         "unset = the workload's measured best: -1 on the scale-16 graph)")
     ap.add_argument("--grid-per-cu", type=int, default=0)
     ap.add_argument("--deg2", action="store_true")
     ap.add_argument("--autotune", type=int, default=0, help="tune batch/alpha/grid on this many sampled sources first")
@@ -329,6 +334,8 @@ def main():
     g, wl, prune, sources = workload(args.config, args.sources)
     if args.batch == 0:
         args.batch = BEST_BATCH.get(args.config, 256)
+    if args.alpha is None:
+        args.alpha = BEST_ALPHA.get(args.config, 0.0)
     n, nnz, m = g.n, g.nnz, g.m
     log(f"workload {wl}: n={n} m={m}")
     ctx = bcm.Context(0)
@@ -374,7 +381,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64+f64", "data": "synthetic",
         "config": {"workload": wl, "n": n, "m": m, "sources": int(st["sources"]), "traversed": int(st["traversed"]),
-                   "mode": args.mode, "batch": tuned["batch"] if tuned else args.batch, "pruned": prune,
+                   "mode": args.mode, "batch": tuned["batch"] if tuned else args.batch,
+                   "bottom_up_alpha": args.alpha, "pruned": prune,
                    "deg2": args.deg2, "autotuned": tuned},
         "gteps_2m": round(2 * gteps, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
