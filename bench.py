@@ -325,7 +325,7 @@ def main():
         summarize_trace(args.summarize_trace, args.profile_name, args.profile_command)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         raise SystemExit(2)
 
     import torch

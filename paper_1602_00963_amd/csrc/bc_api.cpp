@@ -1,5 +1,5 @@
 // C ABI of the library: graph residency, workspace layout, the plain and
-// batched drivers, parity traces and host-side checks.
+// batched launchers, parity traces and host-side checks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
