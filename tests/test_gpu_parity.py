@@ -254,6 +254,34 @@ def test_rmat_scale16_sampled_sources(bcm, ctx, batch):
         assert_close(got2, ref2, what="rmat16 plain")
 
 
+def test_rmat_scale20_pendants_full_size_sampled(bcm, ctx):
+    """The scale-20 R-MAT graph with 30% extra pendants at full size, pruned,
+    in the benchmark's launch shape (256 sources per launch): 256 sampled
+    sources, pendants among them, against the unpruned oracle."""
+    g = gg.workload_rmat20_pendants()
+    S = gg.sample(np.arange(g.n, dtype=np.int32), 256, 21)
+    deg = g.degrees()
+    assert np.sum(deg[S] == 1) > 25
+    say("case rmat20 pendants sampled", g.n, g.m)
+    ref, _ = oracle.bc(g, S, nthreads=8)
+    got, st = run_bc(bcm, ctx, g, S, prune=True, deg1=True, mode="batched", batch=256)
+    assert st["traversed"] < st["sources"]
+    assert_close(got, ref, what="rmat20 pendants pruned")
+
+
+def test_roadlike_grid_full_size_sampled(bcm, ctx):
+    """The 2048 x 2048 road-like lattice at full size: 32 sampled sources in
+    automatic count form (nearly all wrap uint64 and are rerun extended);
+    scores against the oracle's long-double reruns."""
+    g = gg.workload_roadlike_grid()
+    S = gg.sample(g.non_isolated(), 32, 23)
+    say("case grid2048 sampled", g.n, g.m)
+    ref, ovf = oracle.bc(g, S, nthreads=8)
+    got, st = run_bc(bcm, ctx, g, S, mode="batched", batch=256)
+    assert st["overflowed"] > 0 and ovf.any()
+    assert_close(got, ref, what="grid2048")
+
+
 def test_rmat_scale16_hub_sources_traced(bcm, ctx):
     """Per-source d and sigma bit-exact at full size for sources next to the
     highest-degree vertices: their adjacency lists span many work units, so
