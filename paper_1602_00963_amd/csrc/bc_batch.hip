@@ -7,7 +7,7 @@
 // four rotating arrays).
 //
 // Level lists hold (vertex, word) entries, cut into work units of <= 256
-// edges; every wave independently takes units.  An entry (v, k) joins level
+// edges that waves take one at a time.  An entry (v, k) joins level
 // l+1's list when the first lane of word k reaches v there: the atomic OR
 // that turns F_{l+1}(v, k) from zero to non-zero appends it.  Appends are
 // staged in the workgroup's LDS and flushed with one reservation per
