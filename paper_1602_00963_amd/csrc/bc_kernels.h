@@ -131,7 +131,7 @@ struct BatchArgs {
 
 constexpr int kBatchChunk = 256;
 constexpr int kMaxWords = 16;    // batches of up to 1024 sources
-constexpr int kBatchBlock = 512; // threads per workgroup of the batched kernel
+constexpr int kBatchBlock = 1024; // threads per workgroup of the batched kernel (one per CU)
 constexpr int kPlainChunkHost = 64;
 
 hipError_t launch_plain(const PlainArgs& a, bool ext, int grid, int block, hipStream_t st);
