@@ -198,6 +198,34 @@ def test_degree2_derivation_equals_unpruned(bcm, ctx, batch):
     assert_close(got, ref, what="deg1+deg2")
 
 
+@pytest.mark.parametrize("opts", [dict(mode="plain"), dict(mode="batched", batch=64),
+                                  dict(mode="batched", batch=256), dict(mode="batched", batch=256, sigma="extended")],
+                         ids=["plain", "b64", "b256", "b256-ext"])
+def test_bottom_up_levels_forced(bcm, ctx, opts):
+    """Direction switching: with a large threshold every level after the
+    first few is pulled bottom-up; d and sigma stay bit-exact and scores
+    match the oracle on a dense R-MAT graph and on a lattice with pendants
+    (pruned)."""
+    g = gg.rmat(11, 16, 31)
+    S = gg.sample(g.non_isolated(), 300, 32)
+    say("case bottom-up", opts)
+    ref, _ = oracle.bc(g, S)
+    got, st = run_bc(bcm, ctx, g, S, alpha=1000.0, **opts)
+    assert st["bottom_up_levels"] > 0
+    assert_close(got, ref, what=f"bottom-up {opts}")
+    if opts.get("sigma") != "extended":
+        tr = bcm.Graph(ctx, g).trace(S[:64], alpha=1000.0, **opts)
+        for i, s in enumerate(S[:64]):
+            o = oracle.source(g, s)
+            assert np.array_equal(tr["d"][i], o["d"]), f"d differs for source {s}"
+            assert np.array_equal(tr["sigma"][i], o["sigma"]), f"sigma differs for source {s}"
+    gl = gg.disjoint_union(gg.road_grid(28, 24, 0.05, 0.01, 33), gg.star(6))
+    ref, _ = oracle.bc(gl)
+    got, st = run_bc(bcm, ctx, gl, prune=True, deg1=True, alpha=1000.0, **opts)
+    assert st["bottom_up_levels"] > 0
+    assert_close(got, ref, what=f"bottom-up lattice {opts}")
+
+
 def test_sources_with_repeats_and_isolated(bcm, ctx):
     g = gg.disjoint_union(gg.rmat(9, 8, 2), gg.complete(1))
     nz = g.non_isolated()
