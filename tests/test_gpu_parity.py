@@ -240,6 +240,26 @@ def test_sources_with_repeats_and_isolated(bcm, ctx):
         assert st["traversed"] == len(set(int(s) for s in S if deg[s] > 0))
 
 
+@pytest.mark.parametrize("opts", MODES[:3], ids=MODE_IDS[:3])
+def test_degenerate_inputs(bcm, ctx, opts):
+    """One vertex, only isolated vertices, an empty source list, a 2-vertex
+    component under pruning, and a ragged last batch (130 sources)."""
+    say("case degenerate", opts)
+    for g in [gg.complete(1), gg.disjoint_union(*[gg.complete(1) for _ in range(5)])]:
+        got, st = run_bc(bcm, ctx, g, **opts)
+        assert not got.any() and st["sources"] == 0
+    g = gg.rmat(9, 8, 41)
+    got, st = run_bc(bcm, ctx, g, np.zeros(0, dtype=np.int32), **opts)
+    assert not got.any() and st["sources"] == 0 and st["traversed"] == 0
+    got, st = run_bc(bcm, ctx, gg.path(2), prune=True, deg1=True, **opts)
+    assert not got.any()
+    S = gg.sample(g.non_isolated(), 130, 42)
+    ref, _ = oracle.bc(g, S)
+    got, st = run_bc(bcm, ctx, g, S, **opts)
+    assert st["traversed"] == 130
+    assert_close(got, ref, what=f"ragged {opts}")
+
+
 def test_batched_deterministic(bcm, ctx):
     g = gg.rmat(12, 16, 5)
     G = bcm.Graph(ctx, g)
