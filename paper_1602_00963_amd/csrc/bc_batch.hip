@@ -55,7 +55,7 @@ namespace bcx {
 
 constexpr int CHB = kBatchChunk;
 constexpr int kSlots = 4;                          // rotating level-mask arrays
-constexpr int kStageCap = 4096;                    // staged appends per workgroup and phase
+constexpr int kStageCap = 8192;                    // staged appends per workgroup and phase
 constexpr int kWavesPB = kBatchBlock / kWave;
 constexpr int kStagePerThread = kStageCap / kBatchBlock;
 constexpr int kLaneMaxDeg = 32;                    // longest adjacency a single lane walks
