@@ -7,7 +7,7 @@ GTEPS (sources x undirected edges / s), the roofline of the dominant kernel,
 the one-source-per-launch form on a source sample, and the CPU oracle timed
 on the host on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config rmat16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config rmat20p]
 """
 from __future__ import annotations
 
@@ -39,11 +39,11 @@ def workload(name: str, sources_arg: int):
     elif name == "rmat20p":
         g, wl, prune = gg.workload_rmat20_pendants(), "rmat20_ef16_plus30pct_pendants_pruned", True
     elif name == "grid2048":
-        g, wl, prune = gg.workload_roadlike_grid(), "grid2048_roadlike_8192_sources", False
-        if sources_arg <= 0:
-            sources_arg = 8192
+        g, wl, prune = gg.workload_roadlike_grid(), "grid2048_roadlike_all_sources", False
     else:
         raise SystemExit(f"unknown workload {name} (rmat10, rmat16, rmat20p, grid2048)")
+    if sources_arg < 0:
+        sources_arg = DEFAULT_SOURCES.get(name, 0)
     src = None
     if sources_arg > 0:
         src = gg.sample(g.non_isolated(), min(sources_arg, len(g.non_isolated())), 44)
@@ -249,10 +249,25 @@ def serving_run(bcm, ctx, n_graphs: int, max_scale: int, n_queries: int, rho: fl
             "gteps": round(te / span / 1e9, 3), "span_s": round(span, 2)}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(g, m: int, budget_s: float, seed: int = 91):
+    """The oracle (sequential Brandes per source, unpruned graph) timed on
+    the host: on `cores` threads with a static split of a bounded sample of
+    sources, and on one thread on a smaller sample."""
     import graphgen as gg
     import oracle
-    cores = min(os.cpu_count() or 1, 16)
+    nproc = os.cpu_count() or 1
+    cores = min(nproc, 16)   # the GPU box's CPU share for one GPU
     cand = g.non_isolated()
     probe = gg.sample(cand, min(len(cand), 2 * cores), seed)
     t0 = time.perf_counter()
@@ -263,9 +278,18 @@ def cpu_baseline(g, m: int, budget_s: float, seed: int = 91):
     t0 = time.perf_counter()
     oracle.bc(g, S, nthreads=cores)
     dt = time.perf_counter() - t0
+    # one thread, about a quarter of the budget
+    k1 = int(min(len(cand), max(1, k / cores * (budget_s / 4) / max(dt, 1e-3))))
+    S1 = gg.sample(cand, k1, seed + 2)
+    t0 = time.perf_counter()
+    oracle.bc(g, S1, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": k * m / dt / 1e9, "unit": "GTEPS", "cores": cores, "kind": "oracle",
             "sample": f"{k} uniformly sampled sources of the same graph (seed {seed + 1}), sequential Brandes "
-                      f"per source, static split over {cores} threads; {dt:.1f} s"}
+                      f"per source on the unpruned graph, static split over {cores} threads; {dt:.1f} s",
+            "value_1thread": k1 * m / dt1 / 1e9,
+            "sample_1thread": f"{k1} sources (seed {seed + 2}), one thread; {dt1:.1f} s",
+            "nproc": nproc, "cpu_model": cpu_model()}
 
 
 # Settings measured fastest on MI355X.  Batch width (sweep of 128..1024
@@ -276,6 +300,12 @@ def cpu_baseline(g, m: int, budget_s: float, seed: int = 91):
 # and switching the test off (-1) spares the kernel its bookkeeping (+1%).
 BEST_BATCH = {"rmat16": 1024}
 BEST_ALPHA = {"rmat16": -1.0, "rmat20p": -1.0}
+# Sources per step when none are given: the scale-20 graph is measured on a
+# uniform sample (all its 1.1 M non-pruned sources would take about a minute
+# and a half per step), as the paper extrapolates from a sample of sources;
+# the lattice on its 8,192 sampled sources.
+DEFAULT_SOURCES = {"rmat20p": 16384, "grid2048": 8192}
+PLAIN_SAMPLE = {"rmat20p": 512, "grid2048": 64}
 
 
 def main():
@@ -283,9 +313,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="rmat16",
-                    help="workload: rmat10, rmat16 (default), rmat20p (with pendants, pruned), grid2048")
-    ap.add_argument("--sources", type=int, default=0, help="sample this many sources (0 = all)")
+    ap.add_argument("--config", default="rmat20p",
+                    help="workload: rmat10, rmat16, rmat20p (default: scale 20 with pendants, pruned), grid2048")
+    ap.add_argument("--sources", type=int, default=-1,
+                    help="sample this many sources (0 = all; -1 = the workload's default: 16,384 on rmat20p, "
+                         "8,192 on grid2048, all on the others)")
     ap.add_argument("--batch", type=int, default=0,
                     help="sources per launch (0 = the width measured fastest for the workload: "
                          "1024 on the scale-16 graph, 256 on the others)")
@@ -295,8 +327,11 @@ def main():
                          "unset = the workload's measured best: -1 on the R-MAT graphs)")
     ap.add_argument("--grid-per-cu", type=int, default=0)
     ap.add_argument("--deg2", action="store_true")
-    ap.add_argument("--autotune", type=int, default=0, help="tune batch/alpha/grid on this many sampled sources first")
-    ap.add_argument("--plain-sample", type=int, default=2048)
+    ap.add_argument("--autotune", type=int, default=-1,
+                    help="tune batch/alpha/grid on this many sampled sources first (0 = off; -1 = 4,096 "
+                         "when no batch or alpha is given)")
+    ap.add_argument("--plain-sample", type=int, default=0,
+                    help="sources timed one per launch (0 = 512 on rmat20p, 64 on grid2048, else 2,048)")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -333,10 +368,14 @@ def main():
     import paper_1602_00963_amd as bcm
 
     g, wl, prune, sources = workload(args.config, args.sources)
+    if args.autotune < 0:
+        args.autotune = 4096 if (args.batch == 0 and args.alpha is None) else 0
     if args.batch == 0:
         args.batch = BEST_BATCH.get(args.config, 256)
     if args.alpha is None:
         args.alpha = BEST_ALPHA.get(args.config, 0.0)
+    if args.plain_sample <= 0:
+        args.plain_sample = PLAIN_SAMPLE.get(args.config, 2048)
     n, nnz, m = g.n, g.nnz, g.m
     log(f"workload {wl}: n={n} m={m}")
     ctx = bcm.Context(0)
@@ -349,7 +388,8 @@ def main():
         import graphgen as gg
         cand = g.non_isolated() if sources is None else sources
         t0 = time.perf_counter()
-        tuned = G.autotune(gg.sample(cand, min(args.autotune, len(cand)), 17), deg1=prune, deg2=args.deg2)
+        tuned = G.autotune(gg.sample(cand, min(args.autotune, len(cand)), 17), budget_ms=60000.0, deg1=prune,
+                           deg2=args.deg2)
         tuned["seconds"] = round(time.perf_counter() - t0, 2)
         log(f"autotune: {tuned}")
         opts.update(batch=0, alpha=0.0, grid_per_cu=0)
@@ -383,7 +423,7 @@ def main():
         "vs_baseline": None, "dtype": "u64+f64", "data": "synthetic",
         "config": {"workload": wl, "n": n, "m": m, "sources": int(st["sources"]), "traversed": int(st["traversed"]),
                    "mode": args.mode, "batch": tuned["batch"] if tuned else args.batch,
-                   "bottom_up_alpha": args.alpha, "pruned": prune,
+                   "bottom_up_alpha": tuned["alpha"] if tuned else args.alpha, "pruned": prune,
                    "deg2": args.deg2, "autotuned": tuned},
         "gteps_2m": round(2 * gteps, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -391,6 +431,7 @@ def main():
                      "kernel": "batch_kernel" if args.mode == "batched" else "plain_kernel",
                      "avg_launch_ms": round(per_launch_ms, 4), "launches": int(st["launches"]),
                      "kernel_ms_per_step": round(kern_ms, 2), "event_ms_per_step": round(float(np.median(times)), 2),
+                     "launch_gap_us": round((float(np.median(times)) - kern_ms) * 1e3 / max(st["launches"], 1), 1),
                      "alg_bytes_per_launch": round(bytes_run / max(st["launches"], 1)),
                      "bytes_per_te": round(bytes_run / st["raw_te"], 3) if st["raw_te"] else None},
     }
@@ -408,6 +449,7 @@ def main():
         pk = pst["kernel_ms"]
         out["plain"] = {"gteps": round(pg, 3), "sample_sources": int(len(ps)), "ms": round(pms, 1),
                         "avg_launch_ms": round(pk / max(pst["launches"], 1), 4),
+                        "launch_gap_us": round((pms - pk) * 1e3 / max(pst["launches"], 1), 1),
                         "achieved_GBs": round(pbytes / (pk / 1e3) / 1e9, 1)}
         out["batched_over_plain"] = round(gteps / pg, 2)
         log(f"plain: {pg:.2f} GTEPS on {len(ps)} sources")

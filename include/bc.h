@@ -4,11 +4,13 @@
  * The method is Brandes' algorithm as restated in Vella, Carbone, Bernaschi,
  * "Algorithms and Heuristics for Scalable Betweenness Centrality Computation
  * on Multi-GPU Systems" (arXiv:1602.00963):
- *   - scores are sums of per-source dependencies (Sec. 2, Eq. (2)-(3));
- *   - each source runs a level-synchronous shortest-path count (Sec. 3,
- *     Alg. 2-3) and a successor-checking dependency sweep (Alg. 4-5);
- *   - optional 1-degree reduction (Sec. 3.5.1, Eq. (4)-(5), Alg. 6) and
- *     2-degree derivation (Sec. 3.5.2, Lemma 1, Eq. (6), Alg. 7).
+ *   - scores are sums of per-source dependencies (Sec. 2, Eq. (1)-(3));
+ *   - each source runs a level-synchronous shortest-path count (Sec. 3.2,
+ *     Alg. 2-3) and a successor-checking dependency sweep (Sec. 3.2,
+ *     Alg. 4-5);
+ *   - optional 1-degree reduction (Sec. 2.2, Eq. (4)-(5); Sec. 3.4.1,
+ *     Alg. 6) and 2-degree derivation (Sec. 3.4.2, Lemma 1, Eq. (6),
+ *     Alg. 7).
  *
  * Graphs are simple, undirected and unweighted, given as a symmetric CSR
  * (row_ptr[n+1], col_idx[nnz], int32, every pair stored in both directions).
@@ -85,7 +87,7 @@ typedef struct bc_graph_stats {
  * Uploads a graph and keeps it resident in HBM.  With BC_LOAD_VALIDATE the
  * CSR is checked on the host first (BC_E_INVALID_GRAPH, message names the
  * first offending vertex).  With BC_LOAD_PRUNE_DEG1, degree-1 vertices whose
- * neighbour has degree >= 2 are folded into omega(neighbour) (Sec. 3.5.1);
+ * neighbour has degree >= 2 are folded into omega(neighbour) (Sec. 3.4.1);
  * both ends of a 2-vertex component are dropped (their score is 0).
  */
 bc_status bc_graph_load(bc_context* ctx, int32_t n, const int32_t* row_ptr, const int32_t* col_idx,

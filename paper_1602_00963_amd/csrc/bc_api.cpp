@@ -151,12 +151,13 @@ size_t table_bytes(int B) {
 // non-decreasing and a batch has at most K + slots - 1 (word, slot) pairs.
 int32_t cap_pairs_for(int K, int max_slots) { return K + std::min(max_slots, kMaxSlots) - 1; }
 
-size_t batch_layout(int64_t n, int64_t nnz, int B, int cap_factor, int max_slots, char* base, BatchWs* w) {
+size_t batch_layout(int64_t n, int64_t nnz, int B, int cap_factor, int max_slots, bool with_lv, char* base,
+                    BatchWs* w) {
   const int K = B / 64;
   Carve c{base};
   BatchWs t{};
   t.caps = batch_caps(n, nnz, B, cap_factor);
-  t.lv = c.take<int32_t>((size_t)n * B);
+  t.lv = with_lv ? c.take<int32_t>((size_t)n * B) : nullptr;  // per-lane levels: traces only
   t.sig = c.take<uint64_t>((size_t)n * B);
   t.se = c.take<int32_t>((size_t)n * B);
   t.vis = c.take<uint64_t>((size_t)n * K * 5);  // vis then the four level-mask arrays
@@ -228,6 +229,7 @@ struct bc_graph {
   // batching order of sources (computed on the first batched call)
   std::vector<int32_t> rank;
   std::once_flag rank_once;
+  Exec exec;  // launch timing and lane-table staging of calls made under `mu`
   std::mutex mu;
 };
 
@@ -422,6 +424,7 @@ bc_status bc_graph_free(bc_graph* g) {
   for (void* p : {(void*)g->d_rp, (void*)g->d_ci, (void*)g->d_rrp, (void*)g->d_rci, (void*)g->d_omega,
                   (void*)g->d_gu_p, (void*)g->d_gu_b, (void*)g->d_rgu_p, (void*)g->d_rgu_b, (void*)g->d_bc, g->ws})
     if (p) (void)hipFree(p);
+  g->exec.release();
   delete g;
   return BC_OK;
 }
@@ -461,7 +464,7 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
 size_t ws_bytes_for(const bc_graph* g, const Resolved& r, int cap_factor) {
   cap_factor = std::max(cap_factor, r.cap_factor);
   if (r.mode == BC_MODE_PLAIN) return plain_layout(g->n, g->nnz, nullptr, nullptr);
-  return batch_layout(g->n, g->nnz, r.B, cap_factor, r.max_slots, nullptr, nullptr);
+  return batch_layout(g->n, g->nnz, r.B, cap_factor, r.max_slots, r.trace, nullptr, nullptr);
 }
 
 struct TravGraph {
@@ -634,35 +637,48 @@ struct CallOut {
 
 // Launch timing: an event pair recorded on the launch stream around each
 // kernel launch; durations are summed when the host next waits for the
-// stream.  One pool per host thread (the server runs batches from several).
-struct LaunchTimer {
-  std::vector<hipEvent_t> ev;
-  size_t used = 0;
-  ~LaunchTimer() {
-    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+// stream.
+hipError_t Exec::mark(hipStream_t st) {
+  if (used == ev.size()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    ev.push_back(e);
   }
-  hipError_t mark(hipStream_t st) {
-    if (used == ev.size()) {
-      hipEvent_t e;
-      hipError_t r = hipEventCreate(&e);
-      if (r != hipSuccess) return r;
-      ev.push_back(e);
-    }
-    return hipEventRecord(ev[used++], st);
+  return hipEventRecord(ev[used++], st);
+}
+
+hipError_t Exec::collect(double* ms) {
+  for (size_t i = 0; i + 1 < used; i += 2) {
+    float f = 0.f;
+    hipError_t r = hipEventElapsedTime(&f, ev[i], ev[i + 1]);
+    if (r != hipSuccess) return r;
+    *ms += f;
   }
-  // After the stream has been waited for: adds the pairs' durations.
-  hipError_t collect(double* ms) {
-    for (size_t i = 0; i + 1 < used; i += 2) {
-      float f = 0.f;
-      hipError_t r = hipEventElapsedTime(&f, ev[i], ev[i + 1]);
-      if (r != hipSuccess) return r;
-      *ms += f;
-    }
-    used = 0;
-    return hipSuccess;
+  used = 0;
+  return hipSuccess;
+}
+
+bc_status Exec::tables(size_t bytes, char** out) {
+  if (stage_bytes < bytes) {
+    if (stage) (void)hipHostFree(stage);
+    stage = nullptr;
+    stage_bytes = 0;
+    HIPCHK(hipHostMalloc((void**)&stage, bytes, hipHostMallocDefault));
+    stage_bytes = bytes;
   }
-};
-static thread_local LaunchTimer t_timer;
+  *out = stage;
+  return BC_OK;
+}
+
+void Exec::release() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  ev.clear();
+  used = 0;
+  if (stage) (void)hipHostFree(stage);
+  stage = nullptr;
+  stage_bytes = 0;
+}
 
 // Trace destinations (device) for a batch, or nulls.
 struct TraceDev {
@@ -673,35 +689,14 @@ struct TraceDev {
   double* bc = nullptr;  // scratch score array
 };
 
-// Pinned staging for lane tables, one per host thread (the serving loop runs
-// batches from several threads at once).
-struct PinnedStage {
-  char* p = nullptr;
-  size_t bytes = 0;
-  ~PinnedStage() { if (p) (void)hipHostFree(p); }
-};
-static thread_local PinnedStage t_stage;
-
-static bc_status ensure_tables(size_t bytes, char** out) {
-  if (t_stage.bytes < bytes) {
-    if (t_stage.p) (void)hipHostFree(t_stage.p);
-    t_stage.p = nullptr;
-    t_stage.bytes = 0;
-    HIPCHK(hipHostMalloc((void**)&t_stage.p, bytes, hipHostMallocDefault));
-    t_stage.bytes = bytes;
-  }
-  *out = t_stage.p;
-  return BC_OK;
-}
-
 // Runs all groups through the batched kernel.  Scores go to `bc`.
 bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg,
                       const std::vector<Group>& groups, const std::vector<Triple>& triples, char* wsbase,
                       int cap_factor, hipStream_t st, double* const* slot_ptrs, int nslots, const TraceDev* tr,
-                      CallOut* out, std::vector<int32_t>* trace_lane_vertex) {
-  t_timer.used = 0;
+                      Exec* ex, CallOut* out, std::vector<int32_t>* trace_lane_vertex) {
+  ex->used = 0;
   BatchWs w;
-  batch_layout(g->n, g->nnz, r.B, cap_factor, r.max_slots, wsbase, &w);
+  batch_layout(g->n, g->nnz, r.B, cap_factor, r.max_slots, r.trace, wsbase, &w);
   HIPCHK(hipMemsetAsync(w.ctl_begin, 0, w.ctl_bytes, st));
   HIPCHK(hipMemsetAsync(w.vis, 0, w.mask_bytes, st));
   HIPCHK(hipMemsetAsync(w.pair_bc, 0, sizeof(double) * (size_t)w.cap_pairs * g->n, st));
@@ -709,7 +704,7 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   pack_lanes(groups, triples, r.B, &pk);
   if (trace_lane_vertex) trace_lane_vertex->assign(pk.lane_group.begin(), pk.lane_group.end());
   char* stage = nullptr;
-  bc_status s = ensure_tables(w.table_bytes * kTableBatches, &stage);
+  bc_status s = ex->tables(w.table_bytes * kTableBatches, &stage);
   if (s != BC_OK) return s;
   const int grid = grid_for(g, r, ext, true);
   BatchArgs a{};
@@ -747,7 +742,7 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   a.fulledges = w.fulledges;
   a.bar = w.bar;
   a.clear_at_end = tr ? 0 : 1;
-  a.keep_lv = tr ? 1 : 0;
+  a.keep_lv = (tr && w.lv) ? 1 : 0;
   a.alpha = r.alpha;
   a.cap_entries = (int32_t)w.caps.entries;
   a.cap_units = (int32_t)w.caps.units;
@@ -778,12 +773,12 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
         a.sm_out = (ext && tr->sm) ? tr->sm + off : nullptr;
         a.se_out = (ext && tr->se) ? tr->se + off : nullptr;
       }
-      HIPCHK(t_timer.mark(st));
+      HIPCHK(ex->mark(st));
       HIPCHK(launch_batch(a, ext, grid, r.block, st));
-      HIPCHK(t_timer.mark(st));
+      HIPCHK(ex->mark(st));
     }
     HIPCHK(hipStreamSynchronize(st));  // staging buffer reused by the next group
-    HIPCHK(t_timer.collect(&out->kernel_ms));
+    HIPCHK(ex->collect(&out->kernel_ms));
   }
   int32_t cnt = 0, err = 0, fcnt = 0;
   HIPCHK(hipMemcpyAsync(&cnt, w.ovf_count, sizeof cnt, hipMemcpyDeviceToHost, st));
@@ -802,8 +797,8 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
 }
 
 bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg, const std::vector<Group>& groups,
-                    char* wsbase, hipStream_t st, double* bc, double* delta_out, CallOut* out) {
-  t_timer.used = 0;
+                    char* wsbase, hipStream_t st, double* bc, double* delta_out, Exec* ex, CallOut* out) {
+  ex->used = 0;
   PlainWs w;
   plain_layout(g->n, g->nnz, wsbase, &w);
   HIPCHK(hipMemsetAsync(w.ctl_begin, 0, w.ctl_bytes, st));
@@ -849,12 +844,12 @@ bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& t
     a.src = gr.v;
     a.weight = gr.w;
     a.own = gr.own;
-    HIPCHK(t_timer.mark(st));
+    HIPCHK(ex->mark(st));
     HIPCHK(launch_plain(a, ext, grid, r.block, st));
-    HIPCHK(t_timer.mark(st));
-    if (t_timer.used >= 512) {
+    HIPCHK(ex->mark(st));
+    if (ex->used >= 512) {
       HIPCHK(hipStreamSynchronize(st));
-      HIPCHK(t_timer.collect(&out->kernel_ms));
+      HIPCHK(ex->collect(&out->kernel_ms));
     }
   }
   int32_t cnt = 0, err = 0;
@@ -862,7 +857,7 @@ bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& t
   HIPCHK(hipMemcpyAsync(&err, w.err, sizeof err, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(out->st, w.stats, sizeof(out->st), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  HIPCHK(t_timer.collect(&out->kernel_ms));
+  HIPCHK(ex->collect(&out->kernel_ms));
   out->err = err;
   out->ovf.resize(std::min<int32_t>(cnt, g->n + 1));
   if (cnt) HIPCHK(hipMemcpy(out->ovf.data(), w.ovf_list, sizeof(int32_t) * out->ovf.size(), hipMemcpyDeviceToHost));
@@ -911,16 +906,17 @@ static std::vector<Group> groups_at(int32_t n, const std::vector<Group>& groups,
 // list capacity (they add nothing) are rerun once with worst-case lists.
 static bc_status run_groups(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg,
                             const std::vector<Group>& groups, const std::vector<Triple>& triples, void* user_ws,
-                            size_t user_bytes, hipStream_t st, double* const* slots, int nslots, CallOut* out) {
+                            size_t user_bytes, hipStream_t st, double* const* slots, int nslots, Exec* ex,
+                            CallOut* out) {
   char* ws = nullptr;
   bc_status s = get_ws(g, ws_bytes_for(g, r, r.cap_factor), user_ws, user_bytes, &ws);
   if (s != BC_OK) return s;
   if (r.mode == BC_MODE_PLAIN) {
-    s = run_plain(g, r, ext, tg, groups, ws, st, slots[0], nullptr, out);
+    s = run_plain(g, r, ext, tg, groups, ws, st, slots[0], nullptr, ex, out);
     if (s == BC_OK && out->err) return fail(BC_E_CAPACITY, "level-list capacity exceeded");
     return s;
   }
-  s = run_batched(g, r, ext, tg, groups, triples, ws, r.cap_factor, st, slots, nslots, nullptr, out, nullptr);
+  s = run_batched(g, r, ext, tg, groups, triples, ws, r.cap_factor, st, slots, nslots, nullptr, ex, out, nullptr);
   if (s != BC_OK || out->fail.empty()) return s;
   if (user_ws) return fail(BC_E_CAPACITY, "level-list capacity exceeded; some batches added nothing");
   // rerun the failed batches' sources without derivation, with lists sized
@@ -937,7 +933,7 @@ static bc_status run_groups(bc_graph* g, const Resolved& r, bool ext, const Trav
   s = get_ws(g, ws_bytes_for(g, r2, r2.B), nullptr, 0, &ws);
   if (s != BC_OK) return s;
   CallOut o2;
-  s = run_batched(g, r2, ext, tg, again, {}, ws, r2.B, st, slots, nslots, nullptr, &o2, nullptr);
+  s = run_batched(g, r2, ext, tg, again, {}, ws, r2.B, st, slots, nslots, nullptr, ex, &o2, nullptr);
   if (s != BC_OK) return s;
   if (!o2.fail.empty()) return fail(BC_E_CAPACITY, "level-list capacity exceeded at worst-case size");
   out->merge(o2);
@@ -950,7 +946,7 @@ static bc_status run_groups(bc_graph* g, const Resolved& r, bool ext, const Trav
 // the device score array of result slot i (Group::slot).
 bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& groups, int64_t credited,
                          void* workspace, size_t ws_bytes, hipStream_t st, double* const* slots, int nslots,
-                         bc_run_stats* stats) {
+                         Exec* ex, bc_run_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
   HIPCHK(hipSetDevice(g->ctx->device));
   const TravGraph tg = trav(g, r.deg1);
@@ -985,7 +981,7 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
     rp.cap_factor = 64;
     std::vector<Group> head(groups.begin(), groups.begin() + 64);
     rest.assign(groups.begin() + 64, groups.end());
-    s = run_groups(g, workspace ? r : rp, false, tg, head, {}, workspace, ws_bytes, st, slots, nslots, &co);
+    s = run_groups(g, workspace ? r : rp, false, tg, head, {}, workspace, ws_bytes, st, slots, nslots, ex, &co);
     if (s != BC_OK) return s;
     if (2 * co.ovf.size() > head.size()) {
       ext0 = true;
@@ -998,12 +994,12 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
       }
     }
     CallOut c2;
-    s = run_groups(g, rr, ext0, tg, rest, {}, workspace, ws_bytes, st, slots, nslots, &c2);
+    s = run_groups(g, rr, ext0, tg, rest, {}, workspace, ws_bytes, st, slots, nslots, ex, &c2);
     if (s != BC_OK) return s;
     co.merge(c2);
     co.ovf.insert(co.ovf.end(), c2.ovf.begin(), c2.ovf.end());
   } else {
-    s = run_groups(g, r, ext0, tg, groups, triples, workspace, ws_bytes, st, slots, nslots, &co);
+    s = run_groups(g, r, ext0, tg, groups, triples, workspace, ws_bytes, st, slots, nslots, ex, &co);
     if (s != BC_OK) return s;
   }
   add_stats(&rs, co);
@@ -1015,7 +1011,7 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
   if (!ov.empty() && r.sigma_mode == BC_SIGMA_AUTO) {
     std::vector<Group> again = groups_at(g->n, groups, ov);
     CallOut c2;
-    s = run_groups(g, r, true, tg, again, {}, workspace, ws_bytes, st, slots, nslots, &c2);
+    s = run_groups(g, r, true, tg, again, {}, workspace, ws_bytes, st, slots, nslots, ex, &c2);
     if (s != BC_OK) return s;
     add_stats(&rs, c2);
     rs.rerun_extended = (int64_t)again.size();
@@ -1074,7 +1070,7 @@ bc_status bc_compute(bc_graph* g, const int32_t* sources, int64_t k, const bc_co
   int64_t credited = 0;
   map_sources(g->n, g->h_rp.data(), r.deg1 ? &g->pr : nullptr, sources, k, &groups, &credited);
   double* slots[1] = {g->d_bc};
-  return compute_groups(g, r, groups, credited, workspace, ws_bytes, (hipStream_t)stream, slots, 1, stats);
+  return compute_groups(g, r, groups, credited, workspace, ws_bytes, (hipStream_t)stream, slots, 1, &g->exec, stats);
 }
 
 bc_status bc_scores(const bc_graph* g, double* out, int32_t norm, int32_t out_on_device) {
@@ -1128,7 +1124,7 @@ bc_status bc_autotune(bc_graph* g, const int32_t* sample, int64_t k, bc_compute_
     std::vector<Group> gr = groups;
     double* slots[1] = {scratch};
     HIPCHK(hipEventRecord(e0, nullptr));
-    st = compute_groups(g, r, gr, credited, nullptr, 0, nullptr, slots, 1, nullptr);
+    st = compute_groups(g, r, gr, credited, nullptr, 0, nullptr, slots, 1, &g->exec, nullptr);
     HIPCHK(hipEventRecord(e1, nullptr));
     HIPCHK(hipEventSynchronize(e1));
     float f = 0.f;
@@ -1180,6 +1176,7 @@ bc_status bc_trace(bc_graph* g, const int32_t* sources, int64_t k, const bc_comp
   bc_status s = resolve(g, opts, &r);
   if (s != BC_OK) return s;
   if (r.deg1 || r.deg2) return fail(BC_E_INVALID_ARG, "traces run on the unpruned graph without heuristics");
+  r.trace = true;
   for (int64_t i = 0; i < k; ++i)
     if (sources[i] < 0 || sources[i] >= g->n) return fail(BC_E_INVALID_ARG, "source id out of range");
   HIPCHK(hipSetDevice(g->ctx->device));
@@ -1203,7 +1200,7 @@ bc_status bc_trace(bc_graph* g, const int32_t* sources, int64_t k, const bc_comp
         HIPCHK(hipMemset(w.delta, 0, sizeof(double) * n));
         HIPCHK(hipMemset(w.bc_tmp, 0, sizeof(double) * n));
         CallOut co;
-        s = run_plain(g, r, ext, tg, one, ws, st, w.bc_tmp, w.delta, &co);
+        s = run_plain(g, r, ext, tg, one, ws, st, w.bc_tmp, w.delta, &g->exec, &co);
         if (s != BC_OK) return s;
         if (co.err) return fail(BC_E_CAPACITY, "capacity exceeded");
         if (pass == 0 && !ext) ovf_row[i] = co.ovf.empty() ? 0 : 1;
@@ -1230,7 +1227,7 @@ bc_status bc_trace(bc_graph* g, const int32_t* sources, int64_t k, const bc_comp
   // batched traces: every source its own lane, all in result slot 0 (scratch)
   const int B = r.B;
   BatchWs w;
-  batch_layout(n, g->nnz, B, B, r.max_slots, ws, &w);
+  batch_layout(n, g->nnz, B, B, r.max_slots, true, ws, &w);
   const size_t cells = (size_t)B * n;
   double *dd = nullptr, *dbc = nullptr;
   uint64_t* dsg = nullptr;
@@ -1263,7 +1260,7 @@ bc_status bc_trace(bc_graph* g, const int32_t* sources, int64_t k, const bc_comp
       TraceDev tdv{dd, dsg, (double*)dsg, dse, dbc};
       CallOut co;
       std::vector<int32_t> lanes;
-      res = run_batched(g, r, ext, tg, run, {}, ws, B, st, slots, 1, &tdv, &co, &lanes);
+      res = run_batched(g, r, ext, tg, run, {}, ws, B, st, slots, 1, &tdv, &g->exec, &co, &lanes);
       if (res != BC_OK) break;
       if (!co.fail.empty()) { res = fail(BC_E_CAPACITY, "capacity exceeded"); break; }
       if (hipMemcpy(lv.data(), w.lv, sizeof(int32_t) * lv.size(), hipMemcpyDeviceToHost) != hipSuccess ||

@@ -13,6 +13,24 @@ namespace bcx {
 
 bc_status fail(bc_status st, const std::string& msg);
 
+// Launch state of one caller: an event pool that times each kernel launch
+// on its stream, and pinned host staging for the batches' lane tables.  A
+// graph owns one for bc_compute / bc_trace / bc_autotune (which run under
+// the graph's lock), each server worker owns its own.  It is released
+// explicitly by its owner, never by a static or thread-local destructor:
+// those run at process exit, after the HIP runtime (or a profiler attached
+// to it) may already have shut down.
+struct Exec {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  char* stage = nullptr;
+  size_t stage_bytes = 0;
+  hipError_t mark(hipStream_t st);     // records the next event of the pool on st
+  hipError_t collect(double* ms);      // after the stream was waited for: adds the pairs' durations
+  bc_status tables(size_t bytes, char** out);  // pinned staging of at least `bytes`
+  void release();
+};
+
 // Options after defaults and checks.
 struct Resolved {
   int mode, B, K, block, grid_per_cu, sigma_mode;
@@ -20,13 +38,14 @@ struct Resolved {
   double alpha;
   int cap_factor = 32;  // batched level-list capacity: n * min(B, cap_factor) entries
   int max_slots = 1;    // result slots one batch may feed (the server packs up to 64)
+  bool trace = false;   // parity traces: per-lane levels are kept (extra n * B int32)
 };
 bc_status resolve_opts(const bc_graph* g, const bc_compute_opts* o, Resolved* r);
 void graph_groups(const bc_graph* g, const Resolved& r, const int32_t* sources, int64_t k, std::vector<Group>* groups,
                   int64_t* credited);
 bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& groups, int64_t credited,
                          void* workspace, size_t ws_bytes, hipStream_t st, double* const* slots, int nslots,
-                         bc_run_stats* stats);
+                         Exec* ex, bc_run_stats* stats);
 int64_t graph_n(const bc_graph* g);
 int context_device(const bc_context* c);
 int64_t graph_nnz(const bc_graph* g);

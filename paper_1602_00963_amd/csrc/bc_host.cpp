@@ -1,7 +1,7 @@
 // Host-side graph preparation: CSR validation, the 1-degree reduction
-// (Sec. 3.5.1, Alg. 6), mapping requested sources onto traversal sources
-// with weights (Eq. (4)-(5)), and the choice of 2-degree vertices whose
-// forward sweep is derived from their neighbours' (Sec. 3.5.2).
+// (Sec. 3.4.1, Alg. 6), mapping requested sources onto traversal sources
+// with weights (Sec. 2.2, Eq. (4)-(5)), and the choice of 2-degree vertices
+// whose forward sweep is derived from their neighbours' (Sec. 3.4.2).
 #include "bc_host.h"
 
 #include <algorithm>

@@ -50,6 +50,7 @@ struct Worker {
   hipStream_t st = nullptr;
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  Exec exec;
 };
 
 }  // namespace
@@ -199,7 +200,7 @@ void worker_loop(bc_server* s, Worker* w) {
     r.max_slots = 64;
     if (st == BC_OK)
       st = compute_groups(job.g, r, job.lanes, (int64_t)job.lanes.size(), w->ws, w->ws_bytes, w->st,
-                          job.slots.data(), (int)job.slots.size(), nullptr);
+                          job.slots.data(), (int)job.slots.size(), &w->exec, nullptr);
     // queries whose sources are all done download their results
     std::vector<std::shared_ptr<Query>> complete;
     for (auto& q : job.qs) if (q->next >= q->groups.size() || st != BC_OK) complete.push_back(q);
@@ -268,6 +269,7 @@ bc_status bc_server_destroy(bc_server* s) {
   for (auto& w : s->workers) {
     if (w->ws) (void)hipFree(w->ws);
     if (w->st) (void)hipStreamDestroy(w->st);
+    w->exec.release();
   }
   for (auto& q : s->queue)
     if (q->d_out) (void)hipFree(q->d_out);
