@@ -238,6 +238,7 @@ def serving_run(bcm, ctx, n_graphs: int, max_scale: int, n_queries: int, rho: fl
         stats[i] = srv.wait(tickets[i])
     th.join()
     span = time.perf_counter() - t0
+    sst = srv.stats()
     srv.close()
     lat = np.array([s["latency_ms"] for s in stats])
     te = sum(s["te"] for s in stats)
@@ -246,7 +247,8 @@ def serving_run(bcm, ctx, n_graphs: int, max_scale: int, n_queries: int, rho: fl
     return {"graphs": len(graphs), "scales": [s for s, _, _ in specs], "queries": len(qs), "rho": rho,
             "closed_loop_qps": round(cap, 2), "offered_qps": round(rate, 2),
             "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
-            "gteps": round(te / span / 1e9, 3), "span_s": round(span, 2)}
+            "gteps": round(te / span / 1e9, 3), "span_s": round(span, 2),
+            "server": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sst.items()}}
 
 
 def cpu_model() -> str:

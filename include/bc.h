@@ -214,11 +214,29 @@ bc_status bc_prune_deg1_host(int32_t n, const int32_t* row_ptr, const int32_t* c
 /* ------------------------------------------------------------------ serving */
 
 typedef struct bc_server_config {
-  int64_t hbm_budget_bytes;  /* workspace bytes the server may hold at once; 0 = 64 GiB */
-  int32_t max_inflight;      /* concurrent batches (streams); 0 = 4 */
-  int32_t batch;             /* sources per batch; 0 = 256 */
+  int64_t hbm_budget_bytes;  /* device bytes the server may hold at once (workspaces and result
+                                arrays); 0 = 64 GiB */
+  int32_t max_inflight;      /* concurrent batches (streams); 0 = 4.  Each batch's persistent
+                                grid is a 1/max_inflight share of the device's resident
+                                workgroups, so the running batches co-run on the device */
+  int32_t batch;             /* sources per batch, multiple of 64 up to 256; 0 = 256 */
   int32_t queue_capacity;    /* pending queries; 0 = 4096 */
+  uint32_t heuristics;       /* 0, or BC_H_DEG1: queries on graphs loaded with
+                                BC_LOAD_PRUNE_DEG1 use the 1-degree reduction for their source
+                                subsets (Sec. 3.4.1, Eq. (4)-(5) restricted to the subset) */
 } bc_server_config;
+
+typedef struct bc_server_stats {
+  int32_t workers;            /* worker streams */
+  int32_t grid_workgroups;    /* workgroups of each batch's persistent grid */
+  int32_t max_inflight_seen;  /* most batches running at once */
+  int64_t batches;            /* batches run */
+  double mean_inflight;       /* batches running, averaged over the time any batch ran */
+  double busy_ms;             /* time with at least one batch running */
+  int64_t held_bytes;         /* device bytes held now (workspaces, result arrays, pool) */
+  int64_t reclaims;           /* times pooled arrays / idle workspaces were given back */
+  int64_t allocations;        /* device allocations made by the workers */
+} bc_server_stats;
 
 typedef struct bc_query_stats {
   double submit_ms, start_ms, end_ms;  /* host clock, ms since server creation */
@@ -230,9 +248,13 @@ typedef struct bc_query_stats {
 
 /*
  * Continuous-batching server.  Queries (graph, source subset) are admitted
- * by the HBM footprint of the batches they need; sources of queries on the
- * same graph share batches; up to max_inflight batches run concurrently on
- * their own streams.  Each query's RAW scores are written into its `out`
+ * by HBM footprint: a query's result array must fit next to the other
+ * admitted results and one workspace for the largest admitted graph; a
+ * query that could not fit even alone is rejected (BC_E_REJECTED from
+ * bc_wait).  Sources of queries on the same graph share batches; up to
+ * max_inflight batches run concurrently on their own streams.  Device
+ * memory is pooled and reused; no device allocation or free happens while
+ * the server's lock is held.  Each query's RAW scores are written into its `out`
  * array (n doubles, host), which must stay valid until bc_wait returns for
  * its ticket.  A query's result does not depend on which other queries share
  * its batches beyond floating-point summation order (relative 1e-9).
@@ -243,6 +265,8 @@ bc_status bc_server_destroy(bc_server* s);
 bc_status bc_submit(bc_server* s, bc_graph* g, const int32_t* sources, int64_t k, double* out,
                     uint64_t* ticket);
 bc_status bc_wait(bc_server* s, uint64_t ticket, int64_t timeout_us, bc_query_stats* stats);
+/* Counters of the server since creation (thread-safe). */
+bc_status bc_server_stats_get(bc_server* s, bc_server_stats* out);
 
 /* ------------------------------------------------------------------- errors */
 

@@ -28,7 +28,7 @@ RAW, UNDIRECTED = 0, 1
 EXPORTED = ["bc_context_create", "bc_context_destroy", "bc_graph_load", "bc_graph_stats_get", "bc_graph_free",
             "bc_workspace_size", "bc_compute", "bc_scores", "bc_scores_reset", "bc_trace", "bc_validate_csr",
             "bc_prune_deg1_host", "bc_server_create", "bc_server_destroy", "bc_submit", "bc_wait",
-            "bc_status_string", "bc_last_error", "bc_autotune"]
+            "bc_status_string", "bc_last_error", "bc_autotune", "bc_server_stats_get"]
 
 
 class GraphStats(ctypes.Structure):
@@ -58,7 +58,14 @@ class RunStats(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
-                ("batch", ctypes.c_int32), ("queue_capacity", ctypes.c_int32)]
+                ("batch", ctypes.c_int32), ("queue_capacity", ctypes.c_int32), ("heuristics", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("grid_workgroups", ctypes.c_int32),
+                ("max_inflight_seen", ctypes.c_int32), ("batches", ctypes.c_int64), ("mean_inflight", ctypes.c_double),
+                ("busy_ms", ctypes.c_double), ("held_bytes", ctypes.c_int64), ("reclaims", ctypes.c_int64),
+                ("allocations", ctypes.c_int64)]
 
 
 class QueryStats(ctypes.Structure):
@@ -104,6 +111,7 @@ def lib():
             "bc_submit": [vp, vp, vp, i64, vp, vp],
             "bc_wait": [vp, ctypes.c_uint64, i64, vp],
             "bc_autotune": [vp, vp, i64, vp, ctypes.c_double, vp],
+            "bc_server_stats_get": [vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -292,8 +300,8 @@ class Server:
     """Continuous-batching query server (see bc_server_create)."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, max_inflight: int = 0, batch: int = 0,
-                 queue_capacity: int = 0):
-        c = ServerConfig(hbm_budget_bytes, max_inflight, batch, queue_capacity)
+                 queue_capacity: int = 0, deg1: bool = False):
+        c = ServerConfig(hbm_budget_bytes, max_inflight, batch, queue_capacity, H_DEG1 if deg1 else 0)
         self.h = ctypes.c_void_p()
         _check(lib().bc_server_create(ctx.h, ctypes.byref(c), ctypes.byref(self.h)), "bc_server_create")
 
@@ -310,6 +318,11 @@ class Server:
         d = {f: getattr(qs, f) for f, _ in qs._fields_}
         _check(st, "bc_wait")
         return d
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().bc_server_stats_get(self.h, ctypes.byref(st)), "bc_server_stats_get")
+        return {f: getattr(st, f) for f, _ in st._fields_}
 
     def close(self):
         if self.h:

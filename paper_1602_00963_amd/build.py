@@ -24,7 +24,7 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 5) -> str:
+def build(jobs: int = 6) -> str:
     """Compile every source (always) and link libbc.so."""
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -203,6 +204,7 @@ struct bc_context {
   int device = 0;
   int cus = 0;
   std::string arch;
+  uint64_t bar_ticks = 0;  // longest grid-barrier wait, in ticks of the device's wall clock
 };
 
 struct bc_graph {
@@ -290,6 +292,14 @@ bc_status bc_context_create(int device, bc_context** out) {
   c->device = device;
   c->cus = p.multiProcessorCount;
   c->arch = p.gcnArchName;
+  // A persistent grid whose workgroups cannot all be resident (other
+  // persistent work holding the CUs) gives up at a barrier after this long
+  // instead of waiting forever; BC_BARRIER_TIMEOUT_MS overrides 20 s.
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0) khz = 100000;
+  double ms = 20000.0;
+  if (const char* e = getenv("BC_BARRIER_TIMEOUT_MS")) ms = std::max(0.0, atof(e));
+  c->bar_ticks = (uint64_t)(ms * (double)khz);
   *out = c;
   return BC_OK;
 }
@@ -489,7 +499,8 @@ static int grid_for(const bc_graph* g, const Resolved& r, bool ext, bool batched
   hipError_t e = batched ? batch_max_grid(ext, r.block, &bpc) : plain_max_grid(ext, r.block, &bpc);
   if (e != hipSuccess || bpc < 1) bpc = 1;
   int want = r.grid_per_cu > 0 ? r.grid_per_cu : (batched ? bpc : 1);
-  return g->ctx->cus * std::min(want, bpc);
+  const int grid = g->ctx->cus * std::min(want, bpc);
+  return r.grid_total > 0 ? std::min(grid, r.grid_total) : grid;
 }
 
 // Lane packing of one call: a list of batches, each with per-lane group
@@ -741,6 +752,7 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   a.fail_count = w.fail_count;
   a.fulledges = w.fulledges;
   a.bar = w.bar;
+  a.bar_limit = g->ctx->bar_ticks;
   a.clear_at_end = tr ? 0 : 1;
   a.keep_lv = (tr && w.lv) ? 1 : 0;
   a.alpha = r.alpha;
@@ -786,6 +798,7 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   HIPCHK(hipMemcpyAsync(&err, w.err, sizeof err, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(out->st, w.stats, sizeof(out->st), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
+  if (err & kErrBarrier) return fail(BC_E_DEVICE, "grid-barrier wait gave up: the persistent grid was not resident");
   out->err = err;
   out->ovf.resize(std::min<int32_t>(cnt, g->n + 1));
   out->fail.resize(std::min<int32_t>(fcnt, g->n + 1));
@@ -798,7 +811,7 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
 
 bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg, const std::vector<Group>& groups,
                     char* wsbase, hipStream_t st, double* bc, double* delta_out, Exec* ex, CallOut* out) {
-  ex->used = 0;
+  if (ex) ex->used = 0;
   PlainWs w;
   plain_layout(g->n, g->nnz, wsbase, &w);
   HIPCHK(hipMemsetAsync(w.ctl_begin, 0, w.ctl_bytes, st));
@@ -832,6 +845,7 @@ bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& t
   a.ns = w.ns;
   a.stats = w.stats;
   a.bar = w.bar;
+  a.bar_limit = g->ctx->bar_ticks;
   a.bc = bc;
   a.delta_out = delta_out;
   a.alpha = r.alpha;
@@ -844,8 +858,9 @@ bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& t
     a.src = gr.v;
     a.weight = gr.w;
     a.own = gr.own;
-    HIPCHK(ex->mark(st));
+    if (ex) HIPCHK(ex->mark(st));
     HIPCHK(launch_plain(a, ext, grid, r.block, st));
+    if (!ex) continue;
     HIPCHK(ex->mark(st));
     if (ex->used >= 512) {
       HIPCHK(hipStreamSynchronize(st));
@@ -857,7 +872,8 @@ bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& t
   HIPCHK(hipMemcpyAsync(&err, w.err, sizeof err, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(out->st, w.stats, sizeof(out->st), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  HIPCHK(ex->collect(&out->kernel_ms));
+  if (ex) HIPCHK(ex->collect(&out->kernel_ms));
+  if (err & kErrBarrier) return fail(BC_E_DEVICE, "grid-barrier wait gave up: the persistent grid was not resident");
   out->err = err;
   out->ovf.resize(std::min<int32_t>(cnt, g->n + 1));
   if (cnt) HIPCHK(hipMemcpy(out->ovf.data(), w.ovf_list, sizeof(int32_t) * out->ovf.size(), hipMemcpyDeviceToHost));
@@ -1031,6 +1047,8 @@ void graph_groups(const bc_graph* g, const Resolved& r, const int32_t* sources, 
 
 int64_t graph_n(const bc_graph* g) { return g->n; }
 int context_device(const bc_context* c) { return c->device; }
+int context_cus(const bc_context* c) { return c->cus; }
+bool graph_pruned(const bc_graph* g) { return g->pruned; }
 int batch_occupancy(int K) {
   int e = 0, x = 0;
   (void)K;

@@ -38,6 +38,7 @@ struct Resolved {
   double alpha;
   int cap_factor = 32;  // batched level-list capacity: n * min(B, cap_factor) entries
   int max_slots = 1;    // result slots one batch may feed (the server packs up to 64)
+  int grid_total = 0;   // cap on the persistent grid's workgroups (the server's share of the device); 0 = none
   bool trace = false;   // parity traces: per-lane levels are kept (extra n * B int32)
 };
 bc_status resolve_opts(const bc_graph* g, const bc_compute_opts* o, Resolved* r);
@@ -48,6 +49,8 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
                          Exec* ex, bc_run_stats* stats);
 int64_t graph_n(const bc_graph* g);
 int context_device(const bc_context* c);
+int context_cus(const bc_context* c);
+bool graph_pruned(const bc_graph* g);
 int64_t graph_nnz(const bc_graph* g);
 int graph_device(const bc_graph* g);
 size_t graph_ws_bytes(const bc_graph* g, const Resolved& r);

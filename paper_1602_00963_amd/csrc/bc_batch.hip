@@ -740,7 +740,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     stage_flush(a, st, 0, 0, 0);
   }
   if (tid == 0) { a.qoff[0] = 0; a.uoff[0] = 0; }
-  grid_barrier(a.bar);
+  if (!grid_barrier(a.bar, a.bar_limit, a.err)) return;
 
   // ---- forward sweep: phase kl counts level kl and discovers level kl+1
   int kl = 0;
@@ -861,7 +861,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
       C.newl = 0;
     }
     stage_flush(a, st, nl, ebn, ubn);
-    grid_barrier(a.bar);
+    if (!grid_barrier(a.bar, a.bar_limit, a.err)) return;
     eprev2 = eprev;
     eprev = ebase;
     ebase = ebn;
@@ -897,7 +897,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     if (st.ctr[1]) atomicAdd(&a.stats[kStReachedNnz], st.ctr[1]);
     if (st.ctr[2]) atomicAdd(&a.stats[kStDag], st.ctr[2]);
   }
-  grid_barrier(a.bar);
+  if (!grid_barrier(a.bar, a.bar_limit, a.err)) return;
 
   // lanes whose count wrapped (and lanes derived from them) take no part in
   // the backward sweep; the host reruns them in extended form
@@ -917,7 +917,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
       if (EXT) { a.sm_out[(size_t)j * n + v] = r ? a.sm[i] : 0.0; a.se_out[(size_t)j * n + v] = r ? a.se[i] : 0; }
       else a.sig_out[(size_t)j * n + v] = r ? a.sig[i] : 0ull;
     }
-    grid_barrier(a.bar);
+    if (!grid_barrier(a.bar, a.bar_limit, a.err)) return;
   }
 
   // ---- backward sweep
@@ -961,7 +961,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
           clr[(size_t)(uint32_t)ent * K + (ent >> 32)] = 0;
         }
       }
-      grid_barrier(a.bar);
+      if (!grid_barrier(a.bar, a.bar_limit, a.err)) return;
     }
   }
 
@@ -984,7 +984,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     atomicAdd(&a.stats[kStBuLevels], (unsigned long long)bu_levels);
     atomicAdd(&a.stats[kStLaunches], 1ull);
   }
-  grid_barrier(a.bar);  // everything above has read the lane arrays, the level counters and the sums
+  if (!grid_barrier(a.bar, a.bar_limit, a.err)) return;  // everything above has read the lane arrays, the level counters and the sums
   // fold the per-(word, slot) sums into the slots' scores, in word order
   for (int64_t v = tid; v < n; v += nth) {
     for (int p = 0; p < a.npairs; ++p) {
@@ -1016,7 +1016,7 @@ hipError_t launch_batch(const BatchArgs& a, bool ext, int grid, int block, hipSt
     return hipErrorInvalidValue;
   void* args[] = {(void*)&a};
   const void* fn = ext ? (const void*)batch_kernel<true> : (const void*)batch_kernel<false>;
-  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, 0, st);
+  return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, st);
 }
 
 hipError_t batch_max_grid(bool ext, int block, int* blocks_per_cu) {

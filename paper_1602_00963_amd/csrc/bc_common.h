@@ -114,19 +114,27 @@ struct LevelCtr {
 // Every workgroup reads a level's counters only after the barrier that ends
 // the phase building that level, so all of them take the same decisions.
 
-// Grid-wide barrier of a cooperative launch, two-level: the workgroups of
-// one residue class of blockIdx mod 8 (the round-robin order in which
-// workgroups are spread over the eight XCDs) meet on their own counter,
-// the last of each class on a top counter, and the very last bumps a
-// generation word the others poll.  Counters return to 0 by themselves;
-// the generation only grows.  Every wave first waits until its own stores
-// and atomics are performed at the L2 of its XCD; the workgroup's first
-// thread then publishes them to the other XCDs with one agent-scope release
-// fence (an L2 write-back) before arriving, and takes one agent-scope
-// acquire fence (an L1/L2 invalidation, which serves all the workgroup's
-// waves: they run on one CU) after leaving.  A fence in every wave costs a
-// write-back per wave, which dominated the barrier at a thousand
-// workgroups.
+// Grid-wide barrier of a persistent launch (every workgroup resident at
+// once), two-level: the workgroups of one residue class of blockIdx mod 8
+// (the round-robin order in which workgroups are spread over the eight
+// XCDs) meet on their own counter, the last of each class on a top counter,
+// and the very last bumps a generation word the others poll.  Counters
+// return to 0 by themselves; the generation only grows.  Every wave first
+// waits until its own stores and atomics are performed at the L2 of its
+// XCD; the workgroup's first thread then publishes them to the other XCDs
+// with one agent-scope release fence (an L2 write-back) before arriving,
+// and takes one agent-scope acquire fence (an L1/L2 invalidation, which
+// serves all the workgroup's waves: they run on one CU) after leaving.  A
+// fence in every wave costs a write-back per wave, which dominated the
+// barrier at a thousand workgroups.
+//
+// The wait is bounded: a workgroup that has polled for longer than `limit`
+// ticks of the constant-rate wall clock (workgroups of the grid that never
+// became resident, e.g. because other persistent work holds the CUs) raises
+// the abort word and gives up; every later arrival sees the word and gives
+// up at once.  grid_barrier returns false after a give-up, and the kernel
+// then returns, so every workgroup ends normally; the host reports the
+// launch as failed.
 struct alignas(128) BarSlot {
   unsigned v;
   unsigned pad[31];
@@ -135,45 +143,66 @@ struct GridBar {
   BarSlot xcd[8];
   BarSlot top;
   BarSlot gen;
+  BarSlot abort;
 };
 
-__device__ __forceinline__ void grid_barrier(GridBar* b) {
+constexpr int32_t kErrBarrier = 16;  // a grid-barrier wait gave up (DevErr bit)
+
+__device__ __forceinline__ bool grid_barrier(GridBar* b, uint64_t limit, int32_t* err) {
+  __shared__ int s_go;
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned nb = gridDim.x;
-    const unsigned g = __hip_atomic_load(&b->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned x = blockIdx.x & 7u;
-    const unsigned nx = (nb + 7u - x) / 8u;
-    const unsigned ntop = nb < 8u ? nb : 8u;
-    bool last = false;
-    // Arrivals are relaxed: each workgroup's writes were released by the
-    // fence above.  Only the workgroups that pass an arrival on (the last
-    // of an XCD, the last overall) acquire and release again, so that the
-    // others' writes reach the waiters through them.
-    if (__hip_atomic_fetch_add(&b->xcd[x].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nx - 1u) {
-      __hip_atomic_store(&b->xcd[x].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-      if (__hip_atomic_fetch_add(&b->top.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ntop - 1u) {
-        __hip_atomic_store(&b->top.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        last = true;
-      }
-    }
-    if (last) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      __hip_atomic_store(&b->gen.v, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int go = 1;
+    if (__hip_atomic_load(&b->abort.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+      go = 0;
     } else {
-      while (__hip_atomic_load(&b->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
-        __builtin_amdgcn_s_sleep(1);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned nb = gridDim.x;
+      const unsigned g = __hip_atomic_load(&b->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned x = blockIdx.x & 7u;
+      const unsigned nx = (nb + 7u - x) / 8u;
+      const unsigned ntop = nb < 8u ? nb : 8u;
+      bool last = false;
+      // Arrivals are relaxed: each workgroup's writes were released by the
+      // fence above.  Only the workgroups that pass an arrival on (the last
+      // of an XCD, the last overall) acquire and release again, so that the
+      // others' writes reach the waiters through them.
+      if (__hip_atomic_fetch_add(&b->xcd[x].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == nx - 1u) {
+        __hip_atomic_store(&b->xcd[x].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        if (__hip_atomic_fetch_add(&b->top.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ntop - 1u) {
+          __hip_atomic_store(&b->top.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          last = true;
+        }
+      }
+      if (last) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __hip_atomic_store(&b->gen.v, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(&b->gen.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+          if (__hip_atomic_load(&b->abort.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) { go = 0; break; }
+          if (wall_clock64() - t0 > limit) {
+            __hip_atomic_store(&b->abort.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            atomicOr(err, kErrBarrier);
+            go = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_go = go;
   }
   __syncthreads();
+  return s_go != 0;
 }
 
 // Errors raised inside a persistent kernel; the host maps them to bc_status.
 enum DevErr : int32_t { kErrNone = 0, kErrCapEntries = 1, kErrCapUnits = 2, kErrCapPartials = 4, kErrCapMulti = 8 };
+// (kErrBarrier = 16 above: a grid-barrier wait gave up.)
 
 }  // namespace bcx
 

@@ -48,6 +48,7 @@ struct PlainArgs {
   uint64_t* ns;               // component size accumulator (1-degree own term)
   unsigned long long* stats;  // StatIdx counters
   GridBar* bar;
+  uint64_t bar_limit;         // wall-clock ticks a grid-barrier wait may last
   double* bc;
   double* delta_out;          // per-vertex delta of this source (trace), or null
   int32_t src;
@@ -124,6 +125,7 @@ struct BatchArgs {
   int32_t has_own;            // any lane with pendant sources (component sizes needed)
   unsigned long long* fulledges; // edges x words whose word's edge lanes have all reached the vertex
   GridBar* bar;
+  uint64_t bar_limit;         // wall-clock ticks a grid-barrier wait may last
   int32_t clear_at_end;       // clear the masks before returning (off for traces)
   double alpha;
   int32_t cap_entries, cap_units, cap_parts, cap_levels;

@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
     }
   }
   if (tid == 0) { a.qoff[0] = 0; a.uoff[0] = 0; }
-  grid_barrier(a.bar);
+  if (!grid_barrier(a.bar, a.bar_limit, a.err)) return;
 
   // ---- forward sweep
   int l = 0;
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
       }
     }
     if (ballot(wrapped) != 0 && lane == 0) atomicOr(a.ovf_now, 1);
-    grid_barrier(a.bar);
+    if (!grid_barrier(a.bar, a.bar_limit, a.err)) return;
     if (EXT) {
       // counting phase: sigma of the new frontier, pulled from level l
       if (ld_relaxed(&a.lc[nl].err) != 0) { failed = true; break; }
@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
           }
         }
       }
-      grid_barrier(a.bar);
+      if (!grid_barrier(a.bar, a.bar_limit, a.err)) return;
     }
     l = nl;
     ebase = ebn;
@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
       if (r3) atomicAdd((unsigned long long*)a.ns, (unsigned long long)r3);
     }
   }
-  grid_barrier(a.bar);
+  if (!grid_barrier(a.bar, a.bar_limit, a.err)) return;
   const bool overflowed = ld_relaxed(a.ovf_now) != 0;
 
   // ---- backward sweep (skipped when counts wrapped: the host reruns the source)
@@ -311,12 +311,12 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
           }
         }
       }
-      grid_barrier(a.bar);
+      if (!grid_barrier(a.bar, a.bar_limit, a.err)) return;
     }
   }
 
   // ---- epilogue: own term of the 1-degree reduction, reset the control block
-  grid_barrier(a.bar);  // nobody reads ovf_now, ns or the level counters past this point
+  if (!grid_barrier(a.bar, a.bar_limit, a.err)) return;  // nobody reads ovf_now, ns or the level counters past this point
   if (tid == 0) {
     if (!failed && !overflowed && a.own > 0) {
       const double ns = (double)*a.ns;
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
 hipError_t launch_plain(const PlainArgs& a, bool ext, int grid, int block, hipStream_t st) {
   void* args[] = {(void*)&a};
   const void* fn = ext ? (const void*)plain_kernel<true> : (const void*)plain_kernel<false>;
-  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block), args, 0, st);
+  return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, st);
 }
 
 hipError_t plain_max_grid(bool ext, int block, int* blocks_per_cu) {

@@ -42,6 +42,7 @@ def test_struct_layouts_match_header(tmp_path):
     import subprocess
     structs = {"bc_graph_stats": bcmod.GraphStats, "bc_compute_opts": bcmod.ComputeOpts,
                "bc_run_stats": bcmod.RunStats, "bc_server_config": bcmod.ServerConfig,
+               "bc_server_stats": bcmod.ServerStats,
                "bc_query_stats": bcmod.QueryStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bc.h"', 'int main(void) {']
     for cname, py in structs.items():

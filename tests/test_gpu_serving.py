@@ -135,3 +135,97 @@ def test_bad_query_does_not_disturb_others(bcm, ctx):
     assert not empty.out.any()
     srv.close()
     G.close()
+
+
+def _server_ws_bytes(bcm, ctx, G, g, batch):
+    """Device bytes the server holds for one batch on G: a probe server runs
+    one query, then its held bytes are the workspace plus the pooled
+    result array."""
+    srv = bcm.Server(ctx, max_inflight=1, batch=batch)
+    t = srv.submit(G, gg.sample(g.non_isolated(), 8, 1))
+    srv.wait(t, timeout_us=120_000_000)
+    held = srv.stats()["held_bytes"]
+    srv.close()
+    return held - 8 * g.n
+
+
+def test_idle_workspaces_do_not_block_admission(bcm, ctx):
+    """Two workers cache workspaces for two small graphs; the budget is just
+    big enough for a larger graph's query alone.  Its query must be admitted
+    (idle workspaces are given back) and finish: a regression would time out
+    instead of hanging the test."""
+    ga, gb, gc = gg.rmat(10, 8, 21), gg.rmat(10, 8, 22), gg.rmat(12, 8, 23)
+    Ga, Gb, Gc = (bcm.Graph(ctx, g) for g in (ga, gb, gc))
+    wa = _server_ws_bytes(bcm, ctx, Ga, ga, 64)
+    wb = _server_ws_bytes(bcm, ctx, Gb, gb, 64)
+    wc = _server_ws_bytes(bcm, ctx, Gc, gc, 64)
+    assert wc > wa + wb
+    budget = wc + 8 * gc.n + 8 * (ga.n + gb.n)  # fits c alone, not next to a's and b's workspaces
+    assert budget < wa + wb + wc
+    say("case idle workspaces: budget", budget, "ws", wa, wb, wc)
+    srv = bcm.Server(ctx, hbm_budget_bytes=budget, max_inflight=2, batch=64)
+    Sa, Sb = gg.sample(ga.non_isolated(), 300, 1), gg.sample(gb.non_isolated(), 300, 2)
+    ta, tb = srv.submit(Ga, Sa), srv.submit(Gb, Sb)
+    srv.wait(ta, timeout_us=120_000_000)
+    srv.wait(tb, timeout_us=120_000_000)
+    Sc = gg.sample(gc.non_isolated(), 200, 3)
+    tc = srv.submit(Gc, Sc)
+    srv.wait(tc, timeout_us=120_000_000)
+    st = srv.stats()
+    srv.close()
+    assert st["held_bytes"] <= budget
+    for g, S, t in ((ga, Sa, ta), (gb, Sb, tb), (gc, Sc, tc)):
+        ref, _ = oracle.bc(g, S)
+        assert oracle.close(t.out, ref, 1e-9).all()
+    for G in (Ga, Gb, Gc):
+        G.close()
+
+
+def test_batches_run_concurrently(bcm, ctx):
+    """Queries on four graphs submitted together run as concurrent batches
+    (each on a quarter of the device); results equal each query alone."""
+    graphs = [gg.rmat(12, 16, 300 + i) for i in range(4)]
+    Gs = [bcm.Graph(ctx, g) for g in graphs]
+    qs = [(i, gg.sample(graphs[i].non_isolated(), 768, 40 + i)) for i in range(4)] * 2
+    say("case concurrent batches")
+    srv = bcm.Server(ctx, max_inflight=4, batch=256)
+    tickets = [srv.submit(Gs[i], S) for i, S in qs]
+    for t in tickets:
+        srv.wait(t, timeout_us=300_000_000)
+    st = srv.stats()
+    srv.close()
+    say("server stats", st)
+    assert st["workers"] == 4 and st["grid_workgroups"] * 4 <= 256 * 4
+    assert st["max_inflight_seen"] >= 2
+    assert st["mean_inflight"] > 1.0
+    for (i, S), t in zip(qs, tickets):
+        ref = alone(bcm, Gs[i], S)
+        assert oracle.close(t.out, ref, 1e-9).all()
+    for G in Gs:
+        G.close()
+
+
+def test_server_deg1_subsets(bcm, ctx):
+    """Queries on a pruned graph use the 1-degree reduction for their source
+    subsets (pendants, hubs, ends of 2-vertex components among them); each
+    result equals the unpruned oracle on the same subset, alone and mixed."""
+    g = gg.disjoint_union(gg.rmat_with_pendants(11, 8, 3, 0.3, 33), gg.star(9), gg.path(2), gg.path(3))
+    G = bcm.Graph(ctx, g, prune=True)
+    assert G.stats()["pendants"] > 100
+    rng = np.random.default_rng(9)
+    every = np.arange(g.n, dtype=np.int32)
+    subsets = [gg.sample(every, int(rng.integers(50, 900)), 60 + i) for i in range(6)]
+    subsets.append(np.arange(g.n - 15, g.n, dtype=np.int32))  # the star, K2 and the short path
+    say("case server deg1")
+    srv = bcm.Server(ctx, max_inflight=2, batch=128, deg1=True)
+    tickets = [srv.submit(G, S) for S in subsets]
+    for t in tickets:
+        srv.wait(t, timeout_us=300_000_000)
+    srv.close()
+    for S, t in zip(subsets, tickets):
+        ref, _ = oracle.bc(g, S)
+        assert oracle.close(t.out, ref, 1e-9).all(), len(S)
+        G.reset()
+        G.compute(S, mode="batched", batch=128, deg1=True)
+        assert oracle.close(t.out, G.scores(), 1e-9).all()
+    G.close()
