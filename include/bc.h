@@ -160,6 +160,24 @@ bc_status bc_compute(bc_graph* g, const int32_t* sources, int64_t k, const bc_co
                      void* workspace, size_t ws_bytes, void* stream, bc_run_stats* stats);
 
 /*
+ * The plain form with no device allocation, for callers that cannot call
+ * hipMalloc (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation).  Same contract as bc_compute with opts->mode =
+ * BC_MODE_PLAIN (any other mode: BC_E_INVALID_ARG), except:
+ *   - the workspace is a fixed device array of 64 MiB inside the library
+ *     (one per GPU, held until the process ends); a graph whose plain
+ *     workspace (bc_workspace_size) is larger returns BC_E_CAPACITY before
+ *     any device work;
+ *   - the array keeps the last call's contents; every call clears what it
+ *     needs with a fill kernel (no memset node, no allocation, no event);
+ *   - calls on one GPU share the array: the library runs them one at a time
+ *     (a per-device lock held for the whole call); stats->kernel_ms is 0.
+ * The call blocks until its work is complete, like bc_compute.
+ */
+bc_status bc_compute_noalloc(bc_graph* g, const int32_t* sources, int64_t k, const bc_compute_opts* opts,
+                             void* stream, bc_run_stats* stats);
+
+/*
  * Autotuner for the batched mode: times trial runs of `sample` (k source
  * ids, at least two batches' worth recommended) into a scratch score array
  * (the graph's scores are untouched) over batch width {64, 128, 256, 512, 1024},

@@ -28,7 +28,8 @@ RAW, UNDIRECTED = 0, 1
 EXPORTED = ["bc_context_create", "bc_context_destroy", "bc_graph_load", "bc_graph_stats_get", "bc_graph_free",
             "bc_workspace_size", "bc_compute", "bc_scores", "bc_scores_reset", "bc_trace", "bc_validate_csr",
             "bc_prune_deg1_host", "bc_server_create", "bc_server_destroy", "bc_submit", "bc_wait",
-            "bc_status_string", "bc_last_error", "bc_autotune", "bc_server_stats_get"]
+            "bc_status_string", "bc_last_error", "bc_autotune", "bc_compute_noalloc",
+            "bc_server_stats_get"]
 
 
 class GraphStats(ctypes.Structure):
@@ -111,6 +112,7 @@ def lib():
             "bc_submit": [vp, vp, vp, i64, vp, vp],
             "bc_wait": [vp, ctypes.c_uint64, i64, vp],
             "bc_autotune": [vp, vp, i64, vp, ctypes.c_double, vp],
+            "bc_compute_noalloc": [vp, vp, i64, vp, vp, vp],
             "bc_server_stats_get": [vp, vp],
         }
         for name, args in sig.items():
@@ -237,6 +239,21 @@ class Graph:
         ws_bytes = workspace.numel() if workspace is not None else 0
         _check(lib().bc_compute(self.h, _p(src), k, ctypes.byref(o), ws_ptr, ws_bytes, _stream_handle(stream),
                                 ctypes.byref(st)), "bc_compute")
+        return st.as_dict()
+
+    def compute_noalloc(self, sources=None, stream=None, **opts) -> dict:
+        """compute() in the plain form through the entry point that makes no
+        device allocation (workspace = the library's fixed scratch array)."""
+        opts.setdefault("mode", "plain")
+        o = make_opts(**opts)
+        st = RunStats()
+        if sources is None:
+            src, k = None, self.n
+        else:
+            src = _i32(sources)
+            k = len(src)
+        _check(lib().bc_compute_noalloc(self.h, _p(src), k, ctypes.byref(o), _stream_handle(stream),
+                                        ctypes.byref(st)), "bc_compute_noalloc")
         return st.as_dict()
 
     def autotune(self, sample, budget_ms: float = 0.0, **opts) -> dict:

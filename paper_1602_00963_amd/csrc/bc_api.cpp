@@ -286,6 +286,7 @@ bc_status bc_context_create(int device, bc_context** out) {
   HIPCHK(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) return fail(BC_E_INVALID_ARG, "device id out of range");
   HIPCHK(hipSetDevice(device));
+  HIPCHK(noalloc_scratch_init(device));
   hipDeviceProp_t p;
   HIPCHK(hipGetDeviceProperties(&p, device));
   auto* c = new bc_context;
@@ -814,7 +815,8 @@ bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& t
   if (ex) ex->used = 0;
   PlainWs w;
   plain_layout(g->n, g->nnz, wsbase, &w);
-  HIPCHK(hipMemsetAsync(w.ctl_begin, 0, w.ctl_bytes, st));
+  if (r.no_alloc) HIPCHK(zero_async(w.ctl_begin, w.ctl_bytes, st));
+  else HIPCHK(hipMemsetAsync(w.ctl_begin, 0, w.ctl_bytes, st));
   const int grid = grid_for(g, r, ext, false);
   PlainArgs a{};
   a.n = g->n;
@@ -1039,6 +1041,29 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
 }
 
 bc_status resolve_opts(const bc_graph* g, const bc_compute_opts* o, Resolved* r) { return resolve(g, o, r); }
+
+bc_status compute_noalloc(bc_graph* g, const int32_t* sources, int64_t k, const bc_compute_opts* opts, void* scratch,
+                          size_t scratch_bytes, hipStream_t st, bc_run_stats* stats) {
+  std::lock_guard<std::mutex> lk(g->mu);
+  Resolved r;
+  bc_status s = resolve(g, opts, &r);
+  if (s != BC_OK) return s;
+  if (r.mode != BC_MODE_PLAIN) return fail(BC_E_INVALID_ARG, "bc_compute_noalloc runs the plain form only");
+  r.no_alloc = true;
+  const size_t need = ws_bytes_for(g, r, r.cap_factor);
+  if (need > scratch_bytes)
+    return fail(BC_E_CAPACITY, "graph needs " + std::to_string(need) + " bytes of workspace; bc_compute_noalloc holds " +
+                                   std::to_string(scratch_bytes));
+  if (k < 0 || (!sources && k != 0 && k != g->n)) return fail(BC_E_INVALID_ARG, "bad source count");
+  if (!sources) k = g->n;
+  for (int64_t i = 0; sources && i < k; ++i)
+    if (sources[i] < 0 || sources[i] >= g->n) return fail(BC_E_INVALID_ARG, "source id out of range");
+  std::vector<Group> groups;
+  int64_t credited = 0;
+  map_sources(g->n, g->h_rp.data(), r.deg1 ? &g->pr : nullptr, sources, k, &groups, &credited);
+  double* slots[1] = {g->d_bc};
+  return compute_groups(g, r, groups, credited, scratch, scratch_bytes, st, slots, 1, nullptr, stats);
+}
 
 void graph_groups(const bc_graph* g, const Resolved& r, const int32_t* sources, int64_t k, std::vector<Group>* groups,
                   int64_t* credited) {

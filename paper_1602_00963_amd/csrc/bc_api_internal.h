@@ -40,6 +40,7 @@ struct Resolved {
   int max_slots = 1;    // result slots one batch may feed (the server packs up to 64)
   int grid_total = 0;   // cap on the persistent grid's workgroups (the server's share of the device); 0 = none
   bool trace = false;   // parity traces: per-lane levels are kept (extra n * B int32)
+  bool no_alloc = false;  // bc_compute_noalloc: no events, counters cleared by a fill kernel
 };
 bc_status resolve_opts(const bc_graph* g, const bc_compute_opts* o, Resolved* r);
 void graph_groups(const bc_graph* g, const Resolved& r, const int32_t* sources, int64_t k, std::vector<Group>* groups,
@@ -56,5 +57,15 @@ int graph_device(const bc_graph* g);
 size_t graph_ws_bytes(const bc_graph* g, const Resolved& r);
 // Workgroups per CU the batched kernel can keep resident (both count forms).
 int batch_occupancy(int K);
+
+// The entry point that allocates nothing (bc_static.hip): the size of its
+// fixed device scratch array, the per-device lookup of that array's address,
+// a fill kernel that clears device memory, and the compute path it runs
+// (the plain form, workspace = the scratch array).
+constexpr size_t kNoAllocScratchBytes = 64ull << 20;
+hipError_t noalloc_scratch_init(int device);
+hipError_t zero_async(void* p, size_t bytes, hipStream_t st);
+bc_status compute_noalloc(bc_graph* g, const int32_t* sources, int64_t k, const bc_compute_opts* opts, void* scratch,
+                          size_t scratch_bytes, hipStream_t st, bc_run_stats* stats);
 
 }  // namespace bcx
