@@ -191,64 +191,131 @@ def summarize_trace(trace_dir: str, name: str, command: str) -> None:
     print(open(out).read())
 
 
-def serving_run(bcm, ctx, n_graphs: int, max_scale: int, n_queries: int, rho: float, seed: int = 5):
+def serving_run(bcm, ctx, n_graphs: int, max_scale: int, n_queries: int, rhos, warmup_queries: int = 0,
+                max_inflight: int = 4, seed: int = 5, budget_gb: float = 0.0):
     """Poisson stream of BC queries over resident graphs through the
-    continuous-batching server: p50/p99 latency and GTEPS.  The arrival rate
-    is rho times the capacity measured first in a closed loop."""
+    continuous-batching server: p50/p99 latency and GTEPS per offered load.
+    Capacity (queries / s) is measured first in a closed loop on
+    `warmup_queries` queries (all submitted at once); each rho then offers
+    rho times that rate for `n_queries` queries (arrivals seeded)."""
     import threading
     import graphgen as gg
     specs = gg.serving_graph_specs(n_graphs, 5000, 12, max_scale)
     graphs = [gg.rmat(s, ef, sd) for s, ef, sd in specs]
     Gs = [bcm.Graph(ctx, g, validate=False) for g in graphs]
+    log(f"serving: {len(graphs)} graphs resident, scales {sorted(s for s, _, _ in specs)}")
     rng = np.random.default_rng(seed)
-    qs = []
-    for i in range(n_queries):
-        gi = int(rng.integers(len(graphs)))
-        cand = graphs[gi].non_isolated()
-        k = int(min(len(cand), rng.integers(256, 8193)))
-        qs.append((gi, gg.sample(cand, k, 100000 + i)))
-    srv = bcm.Server(ctx, max_inflight=4, batch=256)
-    # closed loop on a prefix: capacity in queries / s
-    warm = qs[: max(8, n_queries // 10)]
+
+    def draw(count, base):
+        qs = []
+        for i in range(count):
+            gi = int(rng.integers(len(graphs)))
+            cand = graphs[gi].non_isolated()
+            k = int(min(len(cand), rng.integers(256, 8193)))
+            qs.append((gi, gg.sample(cand, k, base + i)))
+        return qs
+
+    srv = bcm.Server(ctx, max_inflight=max_inflight, batch=256,
+                     hbm_budget_bytes=int(budget_gb * (1 << 30)) if budget_gb > 0 else 0)
+    warm = draw(max(8, warmup_queries or n_queries // 10), 100000)
     t0 = time.perf_counter()
     tk = [srv.submit(Gs[gi], S) for gi, S in warm]
     for t in tk:
         srv.wait(t)
     cap = len(warm) / (time.perf_counter() - t0)
-    rate = rho * cap
-    gaps = rng.exponential(1.0 / rate, size=len(qs))
-    stats = [None] * len(qs)
-    tickets = [None] * len(qs)
+    log(f"serving: closed loop {len(warm)} queries, capacity {cap:.2f} queries/s")
+    out = {"graphs": len(graphs), "scales": [s for s, _, _ in specs], "efs": [e for _, e, _ in specs],
+           "warmup_queries": len(warm), "closed_loop_qps": round(cap, 2), "loads": []}
+    for rho in rhos:
+        qs = draw(n_queries, 200000 + int(rho * 1000) * 10000)
+        rate = rho * cap
+        gaps = rng.exponential(1.0 / rate, size=len(qs))
+        stats = [None] * len(qs)
+        tickets = [None] * len(qs)
 
-    def submitter():
-        nxt = time.perf_counter()
-        for i, (gi, S) in enumerate(qs):
-            nxt += gaps[i]
-            d = nxt - time.perf_counter()
-            if d > 0:
-                time.sleep(d)
-            tickets[i] = srv.submit(Gs[gi], S)
+        def submitter():
+            nxt = time.perf_counter()
+            for i, (gi, S) in enumerate(qs):
+                nxt += gaps[i]
+                d = nxt - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(Gs[gi], S)
 
-    th = threading.Thread(target=submitter)
-    t0 = time.perf_counter()
-    th.start()
-    for i in range(len(qs)):
-        while tickets[i] is None:
-            time.sleep(0.0005)
-        stats[i] = srv.wait(tickets[i])
-    th.join()
-    span = time.perf_counter() - t0
+        s0 = srv.stats()
+        th = threading.Thread(target=submitter)
+        t0 = time.perf_counter()
+        th.start()
+        for i in range(len(qs)):
+            while tickets[i] is None:
+                time.sleep(0.0005)
+            stats[i] = srv.wait(tickets[i])
+            if (i + 1) % 250 == 0:
+                log(f"serving rho={rho}: {i + 1}/{len(qs)} queries done")
+        th.join()
+        span = time.perf_counter() - t0
+        s1 = srv.stats()
+        lat = np.array([st["latency_ms"] for st in stats])
+        te = sum(st["te"] for st in stats)
+        busy = s1["busy_ms"] - s0["busy_ms"]
+        mean_inf = ((s1["mean_inflight"] * s1["busy_ms"] - s0["mean_inflight"] * s0["busy_ms"]) / busy
+                    if busy > 0 else 0.0)
+        row = {"rho": rho, "queries": len(qs), "offered_qps": round(rate, 2),
+               "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+               "gteps": round(te / span / 1e9, 3), "span_s": round(span, 2),
+               "batches": s1["batches"] - s0["batches"], "mean_inflight": round(mean_inf, 3),
+               "max_inflight_seen": s1["max_inflight_seen"]}
+        log(f"serving: {row}")
+        out["loads"].append(row)
     sst = srv.stats()
     srv.close()
-    lat = np.array([s["latency_ms"] for s in stats])
-    te = sum(s["te"] for s in stats)
     for G in Gs:
         G.close()
-    return {"graphs": len(graphs), "scales": [s for s, _, _ in specs], "queries": len(qs), "rho": rho,
-            "closed_loop_qps": round(cap, 2), "offered_qps": round(rate, 2),
-            "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
-            "gteps": round(te / span / 1e9, 3), "span_s": round(span, 2),
-            "server": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sst.items()}}
+    out["server"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in sst.items()}
+    head = next((r for r in out["loads"] if abs(r["rho"] - 0.8) < 1e-9), out["loads"][0])
+    out.update({"rho": head["rho"], "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "gteps": head["gteps"]})
+    return out
+
+
+def summarize_overlap(trace_dir: str, name: str, command: str) -> None:
+    """Overlap of batch_kernel dispatches in a kernel trace: the time covered
+    by at least one dispatch, the time covered by two or more, and the most
+    running at once.  Writes profiles/<name>.md."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no kernel_trace.csv under {trace_dir}")
+    with open(f[0]) as fh:
+        rows = [r for r in csv.DictReader(fh) if "batch_kernel" in r["Kernel_Name"]]
+    ev = []
+    for r in rows:
+        ev.append((int(r["Start_Timestamp"]), 1))
+        ev.append((int(r["End_Timestamp"]), -1))
+    ev.sort()
+    cur = best = 0
+    cover = {}
+    last = ev[0][0] if ev else 0
+    for t, d in ev:
+        if cur > 0:
+            cover[cur] = cover.get(cur, 0) + (t - last)
+        cur += d
+        best = max(best, cur)
+        last = t
+    any_ns = sum(cover.values())
+    multi_ns = sum(v for k, v in cover.items() if k >= 2)
+    streams = sorted({r["Stream_Id"] for r in rows})
+    grids = sorted({int(r["Grid_Size_X"]) // max(int(r["Workgroup_Size_X"]), 1) for r in rows})
+    out = os.path.join(ROOT, "profiles", f"{name}.md")
+    with open(out, "w") as fo:
+        fo.write(f"# Concurrent batch_kernel dispatches: {name}\n\n    {command}\n\n")
+        fo.write(f"- dispatches: {len(rows)} on {len(streams)} streams; workgroups per dispatch: {grids}\n")
+        fo.write(f"- time with >= 1 dispatch running: {any_ns / 1e6:.1f} ms\n")
+        fo.write(f"- time with >= 2 running: {multi_ns / 1e6:.1f} ms ({100.0 * multi_ns / max(any_ns, 1):.1f}%)\n")
+        fo.write(f"- most running at once: {best}\n")
+        fo.write("- time by number running: " + ", ".join(f"{k}: {v / 1e6:.1f} ms" for k, v in sorted(cover.items()))
+                 + "\n")
+    print(open(out).read())
 
 
 def cpu_model() -> str:
@@ -339,10 +406,18 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, help="only run a copy of this many bytes")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving leg")
+    ap.add_argument("--serving-full", action="store_true",
+                    help="the full serving mix: 32 graphs of scale 12-20, 200 warm-up and 2,000 measured "
+                         "queries at each load 0.5, 0.8, 0.95")
     ap.add_argument("--serving-graphs", type=int, default=8)
     ap.add_argument("--serving-max-scale", type=int, default=15)
     ap.add_argument("--serving-queries", type=int, default=200)
-    ap.add_argument("--serving-rho", type=float, default=0.8)
+    ap.add_argument("--serving-warmup", type=int, default=0)
+    ap.add_argument("--serving-rho", type=float, nargs="+", default=[0.8])
+    ap.add_argument("--serving-inflight", type=int, default=4)
+    ap.add_argument("--serving-budget-gb", type=float, default=0.0)
+    ap.add_argument("--summarize-overlap", metavar="TRACE_DIR", help="write profiles/<--profile-name>.md")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="after the run, copy this many bytes (scales the traffic counters)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -362,6 +437,13 @@ def main():
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.profile_name, args.profile_command)
         return
+    if args.summarize_overlap:
+        summarize_overlap(args.summarize_overlap, args.profile_name, args.profile_command)
+        return
+    if args.serving_full:
+        args.serving_graphs, args.serving_max_scale, args.serving_queries = 32, 20, 2000
+        args.serving_warmup, args.serving_rho = 200, [0.5, 0.8, 0.95]
+        args.serving_budget_gb = args.serving_budget_gb or 200.0
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         raise SystemExit(2)
@@ -369,6 +451,14 @@ def main():
     import torch
     import paper_1602_00963_amd as bcm
 
+    if args.serving_only:
+        ctx = bcm.Context(0)
+        sv = serving_run(bcm, ctx, args.serving_graphs, args.serving_max_scale, args.serving_queries,
+                         args.serving_rho, args.serving_warmup, args.serving_inflight,
+                         budget_gb=args.serving_budget_gb)
+        print(json.dumps({"metric": "BC serving: p50/p99 query latency and GTEPS, 1 GPU", "serving": sv}),
+              flush=True)
+        return
     g, wl, prune, sources = workload(args.config, args.sources)
     if args.autotune < 0:
         args.autotune = 4096 if (args.batch == 0 and args.alpha is None) else 0
@@ -457,7 +547,8 @@ def main():
         log(f"plain: {pg:.2f} GTEPS on {len(ps)} sources")
     if not args.no_serving:
         out["serving"] = serving_run(bcm, ctx, args.serving_graphs, args.serving_max_scale, args.serving_queries,
-                                     args.serving_rho)
+                                     args.serving_rho, args.serving_warmup, args.serving_inflight,
+                                     budget_gb=args.serving_budget_gb)
         log(f"serving: {out['serving']}")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(g, m, args.cpu_budget)

@@ -67,7 +67,10 @@ bc_status bc_context_destroy(bc_context* ctx);
 enum {
   BC_LOAD_VALIDATE = 1u,     /* check symmetry, no self-loops, no duplicates, ids in range */
   BC_LOAD_PRUNE_DEG1 = 2u,   /* build the 1-degree reduction (omega, residual graph), Alg. 6 */
-  BC_LOAD_DEVICE_PTRS = 4u   /* row_ptr / col_idx are device pointers (copied device-to-device) */
+  BC_LOAD_DEVICE_PTRS = 4u,  /* row_ptr / col_idx are device pointers (copied device-to-device) */
+  BC_LOAD_KEEP_ORDER = 8u    /* keep the caller's vertex order on the device (by default the library
+                                renumbers vertices internally by decreasing degree, for cache
+                                locality; ids at this boundary are always the caller's) */
 };
 
 typedef struct bc_graph_stats {

@@ -212,7 +212,9 @@ struct bc_graph {
   int32_t n = 0;
   int64_t nnz = 0;
   bool pruned = false;
-  std::vector<int32_t> h_rp, h_ci;  // original graph (host copy)
+  std::vector<int32_t> h_rp, h_ci;  // the graph on internal ids (host copy)
+  // internal id of each caller vertex id (empty: the caller's order is kept)
+  std::vector<int32_t> perm;
   Pruned pr;
   // device: original graph and (if pruned) the residual graph G'
   int32_t *d_rp = nullptr, *d_ci = nullptr, *d_rrp = nullptr, *d_rci = nullptr, *d_omega = nullptr;
@@ -257,6 +259,53 @@ static bc_status upload(const std::vector<T>& h, T** d, int64_t* resident) {
   *resident += (int64_t)bytes;
   return BC_OK;
 }
+
+// Internal vertex order: decreasing degree, ties by the caller's id.  The
+// vertices touched most often (hubs: every edge to them reads their level
+// masks and counts) then share cache lines at the low ids instead of being
+// spread over the arrays.  perm[caller id] = internal id; rows are re-sorted.
+static void relabel_by_degree(int32_t n, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
+                              std::vector<int32_t>* perm) {
+  std::vector<int32_t> order((size_t)n);
+  for (int32_t v = 0; v < n; ++v) order[v] = v;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+  perm->assign((size_t)n, 0);
+  for (int32_t i = 0; i < n; ++i) (*perm)[order[i]] = i;
+  std::vector<int32_t> nrp((size_t)n + 1, 0), nci(ci.size());
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t v = order[i];
+    int32_t o = nrp[i];
+    for (int32_t e = rp[v]; e < rp[v + 1]; ++e) nci[o++] = (*perm)[ci[e]];
+    std::sort(nci.begin() + nrp[i], nci.begin() + o);
+    nrp[i + 1] = o;
+  }
+  rp.swap(nrp);
+  ci.swap(nci);
+}
+
+// Caller ids -> internal ids.
+static std::vector<int32_t> to_internal(const bc_graph* g, const int32_t* src, int64_t k) {
+  std::vector<int32_t> out(src, src + k);
+  if (!g->perm.empty())
+    for (auto& v : out) v = g->perm[v];
+  return out;
+}
+
+// Each of `rows` rows of n values from internal to caller order, in place.
+template <class T>
+static void rows_to_caller(const bc_graph* g, T* a, int64_t rows) {
+  if (g->perm.empty() || !a) return;
+  const int64_t n = g->n;
+  std::vector<T> tmp((size_t)n);
+  for (int64_t r = 0; r < rows; ++r) {
+    T* row = a + r * n;
+    for (int64_t v = 0; v < n; ++v) tmp[v] = row[g->perm[v]];
+    std::copy(tmp.begin(), tmp.end(), row);
+  }
+}
+
+void scores_to_caller(const bc_graph* g, double* a) { rows_to_caller(g, a, 1); }
 
 }  // namespace bcx
 
@@ -366,6 +415,11 @@ bc_status bc_graph_load(bc_context* ctx, int32_t n, const int32_t* row_ptr, cons
     const int64_t dg = rp[v + 1] - rp[v];
     g->max_degree = std::max(g->max_degree, dg);
     g->isolated += dg == 0;
+  }
+  if (!(flags & BC_LOAD_KEEP_ORDER)) {
+    relabel_by_degree(n, g->h_rp, g->h_ci, &g->perm);
+    rp = g->h_rp.data();
+    ci = g->h_ci.data();
   }
   bc_status st = BC_OK;
   st = upload(g->h_rp, &g->d_rp, &g->resident);
@@ -1058,16 +1112,20 @@ bc_status compute_noalloc(bc_graph* g, const int32_t* sources, int64_t k, const 
   if (!sources) k = g->n;
   for (int64_t i = 0; sources && i < k; ++i)
     if (sources[i] < 0 || sources[i] >= g->n) return fail(BC_E_INVALID_ARG, "source id out of range");
+  std::vector<int32_t> isrc;
+  if (sources) isrc = to_internal(g, sources, k);
   std::vector<Group> groups;
   int64_t credited = 0;
-  map_sources(g->n, g->h_rp.data(), r.deg1 ? &g->pr : nullptr, sources, k, &groups, &credited);
+  map_sources(g->n, g->h_rp.data(), r.deg1 ? &g->pr : nullptr, sources ? isrc.data() : nullptr, k, &groups,
+              &credited);
   double* slots[1] = {g->d_bc};
   return compute_groups(g, r, groups, credited, scratch, scratch_bytes, st, slots, 1, nullptr, stats);
 }
 
 void graph_groups(const bc_graph* g, const Resolved& r, const int32_t* sources, int64_t k, std::vector<Group>* groups,
                   int64_t* credited) {
-  map_sources(g->n, g->h_rp.data(), r.deg1 ? &g->pr : nullptr, sources, k, groups, credited);
+  const std::vector<int32_t> isrc = to_internal(g, sources, k);
+  map_sources(g->n, g->h_rp.data(), r.deg1 ? &g->pr : nullptr, isrc.data(), k, groups, credited);
 }
 
 int64_t graph_n(const bc_graph* g) { return g->n; }
@@ -1109,9 +1167,12 @@ bc_status bc_compute(bc_graph* g, const int32_t* sources, int64_t k, const bc_co
   if (!sources) k = g->n;
   for (int64_t i = 0; sources && i < k; ++i)
     if (sources[i] < 0 || sources[i] >= g->n) return fail(BC_E_INVALID_ARG, "source id out of range");
+  std::vector<int32_t> isrc;
+  if (sources) isrc = to_internal(g, sources, k);
   std::vector<Group> groups;
   int64_t credited = 0;
-  map_sources(g->n, g->h_rp.data(), r.deg1 ? &g->pr : nullptr, sources, k, &groups, &credited);
+  map_sources(g->n, g->h_rp.data(), r.deg1 ? &g->pr : nullptr, sources ? isrc.data() : nullptr, k, &groups,
+              &credited);
   double* slots[1] = {g->d_bc};
   return compute_groups(g, r, groups, credited, workspace, ws_bytes, (hipStream_t)stream, slots, 1, &g->exec, stats);
 }
@@ -1122,6 +1183,7 @@ bc_status bc_scores(const bc_graph* g, double* out, int32_t norm, int32_t out_on
   HIPCHK(hipSetDevice(g->ctx->device));
   std::vector<double> h((size_t)g->n);
   HIPCHK(hipMemcpy(h.data(), g->d_bc, sizeof(double) * g->n, hipMemcpyDeviceToHost));
+  scores_to_caller(g, h.data());
   if (norm == BC_UNDIRECTED) for (auto& x : h) x *= 0.5;
   if (out_on_device) HIPCHK(hipMemcpy(out, h.data(), sizeof(double) * g->n, hipMemcpyHostToDevice));
   else memcpy(out, h.data(), sizeof(double) * g->n);
@@ -1149,7 +1211,8 @@ bc_status bc_autotune(bc_graph* g, const int32_t* sample, int64_t k, bc_compute_
   if (s != BC_OK) return s;
   std::vector<Group> groups;
   int64_t credited = 0;
-  map_sources(g->n, g->h_rp.data(), r0.deg1 ? &g->pr : nullptr, sample, k, &groups, &credited);
+  const std::vector<int32_t> isample = to_internal(g, sample, k);
+  map_sources(g->n, g->h_rp.data(), r0.deg1 ? &g->pr : nullptr, isample.data(), k, &groups, &credited);
   if (groups.empty()) return fail(BC_E_INVALID_ARG, "sample has no non-isolated source");
   double* scratch = nullptr;
   HIPCHK(hipMalloc((void**)&scratch, sizeof(double) * g->n));
@@ -1211,10 +1274,30 @@ bc_status bc_autotune(bc_graph* g, const int32_t* sample, int64_t k, bc_compute_
   return BC_OK;
 }
 
+static bc_status trace_internal(bc_graph* g, const int32_t* sources, int64_t k, const bc_compute_opts* opts,
+                                int32_t* d, uint64_t* sigma, double* sigma_mant, int32_t* sigma_exp, double* delta,
+                                int32_t* overflow);
+
 bc_status bc_trace(bc_graph* g, const int32_t* sources, int64_t k, const bc_compute_opts* opts, int32_t* d,
                    uint64_t* sigma, double* sigma_mant, int32_t* sigma_exp, double* delta, int32_t* overflow) {
   if (!g || !sources || k <= 0) return fail(BC_E_INVALID_ARG, "bad arguments");
+  for (int64_t i = 0; i < k; ++i)
+    if (sources[i] < 0 || sources[i] >= g->n) return fail(BC_E_INVALID_ARG, "source id out of range");
   std::lock_guard<std::mutex> lk(g->mu);
+  const std::vector<int32_t> isrc = to_internal(g, sources, k);
+  bc_status s = trace_internal(g, isrc.data(), k, opts, d, sigma, sigma_mant, sigma_exp, delta, overflow);
+  if (s != BC_OK) return s;
+  rows_to_caller(g, d, k);
+  rows_to_caller(g, sigma, k);
+  rows_to_caller(g, sigma_mant, k);
+  rows_to_caller(g, sigma_exp, k);
+  rows_to_caller(g, delta, k);
+  return BC_OK;
+}
+
+static bc_status trace_internal(bc_graph* g, const int32_t* sources, int64_t k, const bc_compute_opts* opts,
+                                int32_t* d, uint64_t* sigma, double* sigma_mant, int32_t* sigma_exp, double* delta,
+                                int32_t* overflow) {
   Resolved r;
   bc_status s = resolve(g, opts, &r);
   if (s != BC_OK) return s;

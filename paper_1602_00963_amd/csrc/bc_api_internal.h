@@ -51,6 +51,8 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
 int64_t graph_n(const bc_graph* g);
 int context_device(const bc_context* c);
 int context_cus(const bc_context* c);
+// A score array from the library's internal vertex order to the caller's, in place.
+void scores_to_caller(const bc_graph* g, double* a);
 bool graph_pruned(const bc_graph* g);
 int64_t graph_nnz(const bc_graph* g);
 int graph_device(const bc_graph* g);

@@ -812,9 +812,16 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
         const int32_t re = rp[w + 1];
         const int32_t beg = rp[w] + gu.y * CHB;
         const int32_t end = min(re, beg + CHB);
+        // pull the neighbours' level-kl masks; stop once every edge lane of
+        // the word not yet at w has been found on a neighbour
+        const uint64_t want = EL & ~vk;
         uint64_t orr = 0;
-        for (int32_t off = beg + lane; off < end; off += kWave) orr |= cur[(size_t)ci[off] * K + k];
-        const uint64_t nb = wave_or_u64(orr) & EL & ~vk;
+        for (int32_t base = beg; base < end; base += kWave) {
+          const int32_t off = base + lane;
+          if (off < end) orr |= cur[(size_t)ci[off] * K + k];
+          if (base + kWave < end && (wave_or_u64(orr) & want) == want) break;
+        }
+        const uint64_t nb = wave_or_u64(orr) & want;
         bool claimed = false;
         if (nb && lane == 0) {
           const uint64_t old = atomicOr((unsigned long long*)&nxt[wk], (unsigned long long)nb);
@@ -880,16 +887,41 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     }
   }
   if (a.has_own && !failed) {
-    // n_s of each lane: 1 + omega over the vertices the lane reached
+    // n_s of each lane: 1 + omega summed over the vertices the lane reached.
+    // The workgroup's vertex range is cut into 64-vertex chunks shared by its
+    // waves; each lane loads one vertex's mask, then every lane adds the
+    // weights of the chunk's vertices whose mask has its bit.  Totals meet in
+    // LDS (the append stage is free here), one global add per lane.
+    unsigned long long* acc_l = (unsigned long long*)st.e;
+    for (int j = (int)threadIdx.x; j < (int)B; j += (int)blockDim.x) acc_l[j] = 0;
+    __syncthreads();
     const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
     const int64_t v0 = (int64_t)blockIdx.x * per;
     const int64_t v1 = min((int64_t)n, v0 + per);
-    for (int k = wib; k < K; k += kWavesPB) {
+    for (int k = 0; k < K; ++k) {
       unsigned long long acc = 0;
-      for (int64_t v = v0; v < v1; ++v)
-        if ((a.vis[(size_t)v * K + k] >> lane) & 1ull) acc += 1 + (a.omega ? (unsigned long long)a.omega[v] : 0ull);
-      if (acc) atomicAdd(&a.lane_ns[64 * k + lane], acc);
+      for (int64_t c = v0 + 64 * wib; c < v1; c += 64 * kWavesPB) {
+        const int64_t v = c + lane;
+        uint64_t m = 0;
+        int32_t wt = 0;
+        if (v < v1) {
+          m = a.vis[(size_t)v * K + k];
+          wt = 1 + (a.omega ? a.omega[v] : 0);
+        }
+        uint64_t nz = ballot(m != 0);
+        while (nz) {
+          const int i = __builtin_ctzll(nz);
+          nz &= nz - 1;
+          const uint64_t mv = rl64(m, i);
+          const int32_t wv = rl32(wt, i);
+          if ((mv >> lane) & 1ull) acc += (unsigned long long)wv;
+        }
+      }
+      if (acc) atomicAdd(&acc_l[64 * k + lane], acc);
     }
+    __syncthreads();
+    for (int j = (int)threadIdx.x; j < (int)B; j += (int)blockDim.x)
+      if (acc_l[j]) atomicAdd(&a.lane_ns[j], acc_l[j]);
   }
   __syncthreads();
   if (threadIdx.x == 0) {

@@ -286,6 +286,9 @@ bc_status run_job(bc_server* s, Worker* w, Job& job, std::vector<std::shared_ptr
       st = BC_E_DEVICE;
   }
   if (!complete->empty() && hipStreamSynchronize(w->st) != hipSuccess) st = BC_E_DEVICE;
+  if (st == BC_OK)
+    for (auto& q : *complete)
+      if (q->out) scores_to_caller(q->g, q->out);  // the library's vertex order to the caller's
   return st;
 }
 
