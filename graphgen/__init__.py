@@ -283,6 +283,25 @@ def add_pendants(g: Graph, hubs) -> Graph:
                       name=g.name + "_pend")
 
 
+def attach_trees(g: Graph, sizes, seed: int) -> Graph:
+    """Hang one seeded random tree of each given size from a uniformly chosen
+    vertex of g (an edge from the tree's first vertex to it)."""
+    rng = np.random.default_rng(seed)
+    u, v = g.edges()
+    us, vs = [u], [v]
+    n = g.n
+    for i, sz in enumerate(sizes):
+        t = random_tree(int(sz), seed * 1000 + i) if sz > 1 else None
+        if t is not None:
+            tu, tv = t.edges()
+            us.append(tu + n)
+            vs.append(tv + n)
+        us.append(np.array([n], dtype=np.int64))
+        vs.append(np.array([rng.integers(0, g.n)], dtype=np.int64))
+        n += int(sz)
+    return from_pairs(n, np.concatenate(us), np.concatenate(vs), name=g.name + "_trees")
+
+
 # ------------------------------------------------------------- benchmark workloads
 
 def workload_rmat10() -> Graph:

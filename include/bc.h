@@ -68,9 +68,14 @@ enum {
   BC_LOAD_VALIDATE = 1u,     /* check symmetry, no self-loops, no duplicates, ids in range */
   BC_LOAD_PRUNE_DEG1 = 2u,   /* build the 1-degree reduction (omega, residual graph), Alg. 6 */
   BC_LOAD_DEVICE_PTRS = 4u,  /* row_ptr / col_idx are device pointers (copied device-to-device) */
-  BC_LOAD_KEEP_ORDER = 8u    /* keep the caller's vertex order on the device (by default the library
+  BC_LOAD_KEEP_ORDER = 8u,   /* keep the caller's vertex order on the device (by default the library
                                 renumbers vertices internally by decreasing degree, for cache
                                 locality; ids at this boundary are always the caller's) */
+  BC_LOAD_PRUNE_TREES = 16u  /* the 1-degree reduction iterated until no degree-1 vertex is left (the
+                                extension the paper's 1-degree section leaves out in a footnote): every
+                                tree hanging from the rest of the graph is folded into the vertex it
+                                hangs from, whole tree components are removed; removed vertices get
+                                closed-form scores on the host (they are cut vertices) */
 };
 
 typedef struct bc_graph_stats {
@@ -84,6 +89,7 @@ typedef struct bc_graph_stats {
   int64_t deg2_vertices;   /* vertices of degree 2 in the traversed graph */
   int64_t max_degree;
   int64_t resident_bytes;  /* device bytes held by the graph (CSR, G', omega, scores) */
+  int64_t tree_vertices;   /* vertices removed by the iterated reduction (BC_LOAD_PRUNE_TREES) */
 } bc_graph_stats;
 
 /*
@@ -231,6 +237,18 @@ bc_status bc_validate_csr(int32_t n, const int32_t* row_ptr, const int32_t* col_
 bc_status bc_prune_deg1_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
                              int32_t* omega, int32_t* kind, int32_t* hub,
                              int32_t* res_row_ptr, int32_t* res_col_idx, int64_t* res_nnz);
+
+/*
+ * The iterated reduction on the host (BC_LOAD_PRUNE_TREES): degree-1
+ * vertices are peeled until none is left.  Outputs (caller-allocated, any
+ * may be NULL): omega[n] (vertices folded into each kept vertex: the size of
+ * the forest hanging from it), kind[n] (0 kept, 3 isolated, 4 removed),
+ * scores[n] (RAW scores of the removed vertices for the k sources, or for
+ * every vertex when k = 0; 0 at kept vertices), *res_nnz (directed entries
+ * of the residual graph).  No device work.
+ */
+bc_status bc_prune_trees_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* sources,
+                              int64_t k, int32_t* omega, int32_t* kind, double* scores, int64_t* res_nnz);
 
 /* ------------------------------------------------------------------ serving */
 

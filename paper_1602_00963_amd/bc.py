@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libbc.so")
 # status codes (include/bc.h)
 OK, E_INVALID_ARG, E_INVALID_GRAPH, E_OUT_OF_MEMORY, E_DEVICE, E_BUSY, E_NOT_FOUND, E_TIMEOUT, E_REJECTED, \
     E_CAPACITY = range(10)
-LOAD_VALIDATE, LOAD_PRUNE_DEG1, LOAD_DEVICE_PTRS = 1, 2, 4
+LOAD_VALIDATE, LOAD_PRUNE_DEG1, LOAD_DEVICE_PTRS, LOAD_KEEP_ORDER, LOAD_PRUNE_TREES = 1, 2, 4, 8, 16
 MODE_PLAIN, MODE_BATCHED = 0, 1
 H_DEG1, H_DEG2 = 1, 2
 SIGMA_AUTO, SIGMA_EXACT_ONLY, SIGMA_EXTENDED = 0, 1, 2
@@ -29,12 +29,13 @@ EXPORTED = ["bc_context_create", "bc_context_destroy", "bc_graph_load", "bc_grap
             "bc_workspace_size", "bc_compute", "bc_scores", "bc_scores_reset", "bc_trace", "bc_validate_csr",
             "bc_prune_deg1_host", "bc_server_create", "bc_server_destroy", "bc_submit", "bc_wait",
             "bc_status_string", "bc_last_error", "bc_autotune", "bc_compute_noalloc",
-            "bc_server_stats_get"]
+            "bc_server_stats_get", "bc_prune_trees_host"]
 
 
 class GraphStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in ("n", "m", "nnz", "isolated", "pendants", "k2_vertices",
-                                                 "residual_nnz", "deg2_vertices", "max_degree", "resident_bytes")]
+                                                 "residual_nnz", "deg2_vertices", "max_degree", "resident_bytes",
+                                                 "tree_vertices")]
 
 
 class ComputeOpts(ctypes.Structure):
@@ -114,6 +115,7 @@ def lib():
             "bc_autotune": [vp, vp, i64, vp, ctypes.c_double, vp],
             "bc_compute_noalloc": [vp, vp, i64, vp, vp, vp],
             "bc_server_stats_get": [vp, vp],
+            "bc_prune_trees_host": [i32, vp, vp, vp, i64, vp, vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -164,6 +166,19 @@ def prune_deg1_host(n: int, row_ptr, col_idx) -> dict:
     return {"omega": omega, "kind": kind, "hub": hub, "row_ptr": rrp, "col_idx": rci[:rnnz.value].copy()}
 
 
+def prune_trees_host(n: int, row_ptr, col_idx, sources=None) -> dict:
+    """The iterated 1-degree reduction on the host: omega, kind and the
+    closed-form scores of the removed vertices for `sources` (None = all)."""
+    rp, ci = _i32(row_ptr), _i32(col_idx)
+    src = None if sources is None else _i32(sources)
+    omega, kind = np.zeros(n, np.int32), np.zeros(n, np.int32)
+    sc = np.zeros(n, np.float64)
+    rnnz = ctypes.c_int64(0)
+    _check(lib().bc_prune_trees_host(n, _p(rp), _p(ci), _p(src), 0 if src is None else len(src), _p(omega),
+                                     _p(kind), _p(sc), ctypes.byref(rnnz)), "bc_prune_trees_host")
+    return {"omega": omega, "kind": kind, "scores": sc, "residual_nnz": rnnz.value}
+
+
 class Context:
     def __init__(self, device: int = 0):
         self.h = ctypes.c_void_p()
@@ -203,12 +218,18 @@ def _stream_handle(stream):
 class Graph:
     """A graph resident in HBM.  `g` is anything with n, row_ptr, col_idx."""
 
-    def __init__(self, ctx: Context, g, validate: bool = True, prune: bool = False):
+    def __init__(self, ctx: Context, g, validate: bool = True, prune=False, keep_order: bool = False):
+        """prune: False, True (one round of the 1-degree reduction) or "trees"
+        (the reduction iterated until no degree-1 vertex is left)."""
         self.ctx = ctx
         self.n = int(g.n)
         self.rp = _i32(g.row_ptr)
         self.ci = _i32(g.col_idx)
-        flags = (LOAD_VALIDATE if validate else 0) | (LOAD_PRUNE_DEG1 if prune else 0)
+        flags = (LOAD_VALIDATE if validate else 0) | (LOAD_KEEP_ORDER if keep_order else 0)
+        if prune == "trees":
+            flags |= LOAD_PRUNE_TREES
+        elif prune:
+            flags |= LOAD_PRUNE_DEG1
         self.h = ctypes.c_void_p()
         _check(lib().bc_graph_load(ctx.h, self.n, _p(self.rp), _p(self.ci), int(self.rp[-1]), flags,
                                    ctypes.byref(self.h)), "bc_graph_load")

@@ -138,14 +138,14 @@ struct BatchWs {
   BatchCaps caps;
 };
 
-// One batch's lane table: lane_src[B], lane_own[B], l0[B] (int32), lane_w[B]
-// (double), lane_pair[B] (int16), lane_pa[B], lane_pb[B], lane_slot[B]
+// One batch's lane table: lane_src[B], lane_own[B], l0[B] (int32), lane_w[B],
+// lane_tsub[B] (double), lane_pair[B] (int16), lane_pa[B], lane_pb[B], lane_slot[B]
 // (int8), pair_slot[kMaxPairs] (int8), then 8-aligned edge_lanes[16]
 // (uint64) and slot_bc[64] (device pointers).
 constexpr int kMaxSlots = 64;
 constexpr int kMaxPairs = kMaxWords + kMaxSlots;
 size_t table_bytes(int B) {
-  return align_up((size_t)B * (4 + 4 + 4 + 8 + 2 + 1 + 1 + 1) + kMaxPairs + 8 + 8 * kMaxWords + 8 * kMaxSlots, 256);
+  return align_up((size_t)B * (4 + 4 + 4 + 8 + 8 + 2 + 1 + 1 + 1) + kMaxPairs + 8 + 8 * kMaxWords + 8 * kMaxSlots, 256);
 }
 
 // Lanes are packed slot by slot, so the slots met along the words are
@@ -222,7 +222,10 @@ struct bc_graph {
   int32_t ngu_p = 0, ngu_b = 0, nrgu_p = 0, nrgu_b = 0;
   double* d_bc = nullptr;
   int64_t resident = 0;
-  int64_t max_degree = 0, isolated = 0, pendants = 0, k2 = 0, deg2 = 0, rnnz = 0;
+  int64_t max_degree = 0, isolated = 0, pendants = 0, k2 = 0, deg2 = 0, rnnz = 0, tree = 0;
+  // scores of the vertices removed by the iterated reduction (host, internal
+  // order), accumulated like the device scores until bc_scores_reset
+  std::vector<double> h_tree;
   // library-owned cached workspace
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -307,6 +310,23 @@ static void rows_to_caller(const bc_graph* g, T* a, int64_t rows) {
 
 void scores_to_caller(const bc_graph* g, double* a) { rows_to_caller(g, a, 1); }
 
+// Scores of the vertices the iterated reduction removed (closed form, host),
+// for internal source ids (nullptr: all), added to the graph's accumulator.
+static void add_tree_scores(bc_graph* g, const Resolved& r, const int32_t* isrc, int64_t k) {
+  if (!r.deg1 || !g->pr.trees) return;
+  if (g->h_tree.empty()) g->h_tree.assign((size_t)g->n, 0.0);
+  tree_scores(g->n, g->pr, isrc, isrc ? k : g->n, g->h_tree.data());
+}
+
+void tree_scores_caller(const bc_graph* g, const int32_t* sources, int64_t k, std::vector<double>* out) {
+  out->clear();
+  if (!g->pruned || !g->pr.trees) return;
+  const std::vector<int32_t> isrc = to_internal(g, sources, k);
+  out->assign((size_t)g->n, 0.0);
+  tree_scores(g->n, g->pr, isrc.data(), k, out->data());
+  scores_to_caller(g, out->data());
+}
+
 }  // namespace bcx
 
 extern "C" {
@@ -381,6 +401,23 @@ bc_status bc_prune_deg1_host(int32_t n, const int32_t* row_ptr, const int32_t* c
   return BC_OK;
 }
 
+bc_status bc_prune_trees_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* sources,
+                              int64_t k, int32_t* omega, int32_t* kind, double* scores, int64_t* res_nnz) {
+  if (!row_ptr || !col_idx || n < 0 || k < 0 || (k > 0 && !sources)) return fail(BC_E_INVALID_ARG, "bad arguments");
+  for (int64_t i = 0; i < k; ++i)
+    if (sources[i] < 0 || sources[i] >= n) return fail(BC_E_INVALID_ARG, "source id out of range");
+  Pruned p;
+  prune_trees(n, row_ptr, col_idx, &p);
+  if (omega) memcpy(omega, p.omega.data(), sizeof(int32_t) * n);
+  if (kind) memcpy(kind, p.kind.data(), sizeof(int32_t) * n);
+  if (scores) {
+    std::fill(scores, scores + n, 0.0);
+    tree_scores(n, p, k ? sources : nullptr, k ? k : n, scores);
+  }
+  if (res_nnz) *res_nnz = (int64_t)p.ci.size();
+  return BC_OK;
+}
+
 bc_status bc_graph_load(bc_context* ctx, int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
                         int64_t nnz, uint32_t flags, bc_graph** out) {
   if (!ctx || !out || n <= 0 || !row_ptr || (nnz > 0 && !col_idx)) return fail(BC_E_INVALID_ARG, "bad arguments");
@@ -432,12 +469,14 @@ bc_status bc_graph_load(bc_context* ctx, int32_t n, const int32_t* row_ptr, cons
     if (st == BC_OK) st = upload(ub, &g->d_gu_b, &g->resident);
   }
   const int32_t* trp = rp;
-  if (st == BC_OK && (flags & BC_LOAD_PRUNE_DEG1)) {
+  if (st == BC_OK && (flags & (BC_LOAD_PRUNE_DEG1 | BC_LOAD_PRUNE_TREES))) {
     g->pruned = true;
-    prune_deg1(n, rp, ci, &g->pr);
+    if (flags & BC_LOAD_PRUNE_TREES) prune_trees(n, rp, ci, &g->pr);
+    else prune_deg1(n, rp, ci, &g->pr);
     for (int32_t v = 0; v < n; ++v) {
       g->pendants += g->pr.kind[v] == kPendant;
       g->k2 += g->pr.kind[v] == kK2;
+      g->tree += g->pr.kind[v] == kTree;
     }
     g->rnnz = (int64_t)g->pr.ci.size();
     st = upload(g->pr.rp, &g->d_rrp, &g->resident);
@@ -479,6 +518,7 @@ bc_status bc_graph_stats_get(const bc_graph* g, bc_graph_stats* out) {
   out->residual_nnz = g->rnnz;
   out->deg2_vertices = g->deg2;
   out->max_degree = g->max_degree;
+  out->tree_vertices = g->tree;
   out->resident_bytes = g->resident;
   return BC_OK;
 }
@@ -607,7 +647,7 @@ static void pack_lanes(const std::vector<Group>& groups, const std::vector<Tripl
 
 struct TablePtrs {
   int32_t *lane_src, *lane_own, *l0;
-  double* lane_w;
+  double *lane_w, *lane_tsub;
   int16_t* pair;
   int8_t *pa, *pb, *slot, *pair_slot;
   uint64_t* el;
@@ -620,7 +660,8 @@ static TablePtrs table_at(char* t, int B) {
   p.lane_own = p.lane_src + B;
   p.l0 = p.lane_own + B;
   p.lane_w = (double*)(p.l0 + B);
-  p.pair = (int16_t*)(p.lane_w + B);
+  p.lane_tsub = p.lane_w + B;
+  p.pair = (int16_t*)(p.lane_tsub + B);
   p.pa = (int8_t*)(p.pair + B);
   p.pb = p.pa + B;
   p.slot = p.pb + B;
@@ -653,9 +694,10 @@ static TableInfo fill_table(char* dst, const Packing& pk, int64_t b, const std::
     t.pb[j] = pk.pb[(size_t)b * B + j];
     t.slot[j] = 0;
     t.pair[j] = (int16_t)std::max(info.npairs - 1, 0);
-    if (gi < 0) { t.lane_src[j] = -1; t.lane_own[j] = 0; t.lane_w[j] = 0.0; continue; }
+    if (gi < 0) { t.lane_src[j] = -1; t.lane_own[j] = 0; t.lane_w[j] = 0.0; t.lane_tsub[j] = 0.0; continue; }
     t.lane_src[j] = groups[gi].v;
     t.lane_own[j] = groups[gi].own;
+    t.lane_tsub[j] = groups[gi].tsub;
     t.lane_w[j] = groups[gi].w;
     t.slot[j] = (int8_t)groups[gi].slot;
     if ((j >> 6) != cur_word || groups[gi].slot != cur_slot) {
@@ -680,6 +722,7 @@ static void table_ptrs(char* dev, int B, BatchArgs* a) {
   TablePtrs t = table_at(dev, B);
   a->lane_src = t.lane_src;
   a->lane_own = t.lane_own;
+  a->lane_tsub = t.lane_tsub;
   a->lane_w = t.lane_w;
   a->lane_pa = t.pa;
   a->lane_pb = t.pb;
@@ -914,6 +957,7 @@ bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& t
     a.src = gr.v;
     a.weight = gr.w;
     a.own = gr.own;
+    a.tsub = gr.tsub;
     if (ex) HIPCHK(ex->mark(st));
     HIPCHK(launch_plain(a, ext, grid, r.block, st));
     if (!ex) continue;
@@ -1119,7 +1163,9 @@ bc_status compute_noalloc(bc_graph* g, const int32_t* sources, int64_t k, const 
   map_sources(g->n, g->h_rp.data(), r.deg1 ? &g->pr : nullptr, sources ? isrc.data() : nullptr, k, &groups,
               &credited);
   double* slots[1] = {g->d_bc};
-  return compute_groups(g, r, groups, credited, scratch, scratch_bytes, st, slots, 1, nullptr, stats);
+  bc_status s2 = compute_groups(g, r, groups, credited, scratch, scratch_bytes, st, slots, 1, nullptr, stats);
+  if (s2 == BC_OK) add_tree_scores(g, r, sources ? isrc.data() : nullptr, k);
+  return s2;
 }
 
 void graph_groups(const bc_graph* g, const Resolved& r, const int32_t* sources, int64_t k, std::vector<Group>* groups,
@@ -1174,7 +1220,10 @@ bc_status bc_compute(bc_graph* g, const int32_t* sources, int64_t k, const bc_co
   map_sources(g->n, g->h_rp.data(), r.deg1 ? &g->pr : nullptr, sources ? isrc.data() : nullptr, k, &groups,
               &credited);
   double* slots[1] = {g->d_bc};
-  return compute_groups(g, r, groups, credited, workspace, ws_bytes, (hipStream_t)stream, slots, 1, &g->exec, stats);
+  bc_status s2 = compute_groups(g, r, groups, credited, workspace, ws_bytes, (hipStream_t)stream, slots, 1, &g->exec,
+                                stats);
+  if (s2 == BC_OK) add_tree_scores(g, r, sources ? isrc.data() : nullptr, k);
+  return s2;
 }
 
 bc_status bc_scores(const bc_graph* g, double* out, int32_t norm, int32_t out_on_device) {
@@ -1183,6 +1232,8 @@ bc_status bc_scores(const bc_graph* g, double* out, int32_t norm, int32_t out_on
   HIPCHK(hipSetDevice(g->ctx->device));
   std::vector<double> h((size_t)g->n);
   HIPCHK(hipMemcpy(h.data(), g->d_bc, sizeof(double) * g->n, hipMemcpyDeviceToHost));
+  if (!g->h_tree.empty())
+    for (int64_t v = 0; v < g->n; ++v) h[v] += g->h_tree[v];
   scores_to_caller(g, h.data());
   if (norm == BC_UNDIRECTED) for (auto& x : h) x *= 0.5;
   if (out_on_device) HIPCHK(hipMemcpy(out, h.data(), sizeof(double) * g->n, hipMemcpyHostToDevice));
@@ -1194,6 +1245,7 @@ bc_status bc_scores_reset(bc_graph* g) {
   if (!g) return fail(BC_E_INVALID_ARG, "null graph");
   HIPCHK(hipSetDevice(g->ctx->device));
   HIPCHK(hipMemset(g->d_bc, 0, sizeof(double) * g->n));
+  std::fill(g->h_tree.begin(), g->h_tree.end(), 0.0);
   return BC_OK;
 }
 

@@ -53,6 +53,10 @@ int context_device(const bc_context* c);
 int context_cus(const bc_context* c);
 // A score array from the library's internal vertex order to the caller's, in place.
 void scores_to_caller(const bc_graph* g, double* a);
+// Closed-form scores of the vertices removed by the iterated reduction for a
+// source list (caller ids), in the caller's order; empty unless the graph
+// was loaded with BC_LOAD_PRUNE_TREES.
+void tree_scores_caller(const bc_graph* g, const int32_t* sources, int64_t k, std::vector<double>* out);
 bool graph_pruned(const bc_graph* g);
 int64_t graph_nnz(const bc_graph* g);
 int graph_device(const bc_graph* g);

@@ -1009,7 +1009,10 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
         const int32_t q = atomicAdd(a.ovf_count, 1);
         a.ovf_list[q] = s;
       } else if (a.has_own && a.lane_own[j] != 0) {
-        a.pair_bc[(size_t)a.lane_pair[j] * n + s] += (double)a.lane_own[j] * ((double)a.lane_ns[j] - 2.0);
+        // each folded source reaches its component through s, except s and
+        // its own subtree (Eq. (4) for pendants: own * (n_s - 2))
+        a.pair_bc[(size_t)a.lane_pair[j] * n + s] +=
+            (double)a.lane_own[j] * ((double)a.lane_ns[j] - 1.0) - a.lane_tsub[j];
       }
     }
     atomicAdd(&a.stats[kStLevels], (unsigned long long)levels);

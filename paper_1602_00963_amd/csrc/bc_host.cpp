@@ -113,32 +113,176 @@ void prune_deg1(int32_t n, const int32_t* rp, const int32_t* ci, Pruned* out) {
   }
 }
 
+void prune_trees(int32_t n, const int32_t* rp, const int32_t* ci, Pruned* out) {
+  out->trees = true;
+  out->omega.assign((size_t)n, 0);
+  out->kind.assign((size_t)n, kKept);
+  out->hub.assign((size_t)n, -1);
+  out->parent.assign((size_t)n, -1);
+  out->core.assign((size_t)n, -1);
+  out->top.assign((size_t)n, -1);
+  out->sub.assign((size_t)n, 1);
+  out->comp.assign((size_t)n, 0);
+  out->order.clear();
+  std::vector<int32_t> deg((size_t)n), queue;
+  for (int32_t v = 0; v < n; ++v) {
+    deg[v] = rp[v + 1] - rp[v];
+    if (deg[v] == 0) out->kind[v] = kIsolated;
+    if (deg[v] == 1) queue.push_back(v);
+  }
+  // peel: a vertex left with one neighbour hangs from it; a vertex left with
+  // none is the last vertex of a tree component (its root)
+  for (size_t h = 0; h < queue.size(); ++h) {
+    const int32_t u = queue[h];
+    if (out->kind[u] != kKept || deg[u] != 1) continue;
+    int32_t p = -1;
+    for (int32_t e = rp[u]; e < rp[u + 1]; ++e)
+      if (out->kind[ci[e]] == kKept) { p = ci[e]; break; }
+    out->kind[u] = kTree;
+    out->parent[u] = p;
+    out->order.push_back(u);
+    out->sub[p] += out->sub[u];
+    if (--deg[p] == 1) queue.push_back(p);
+    if (deg[p] == 0) {
+      out->kind[p] = kTree;  // root of a tree component
+      out->order.push_back(p);
+    }
+  }
+  // component sizes of the original graph
+  std::vector<int32_t> stack;
+  std::vector<char> seen((size_t)n, 0);
+  std::vector<int32_t> members;
+  for (int32_t s = 0; s < n; ++s) {
+    if (seen[s]) continue;
+    members.clear();
+    stack.assign(1, s);
+    seen[s] = 1;
+    while (!stack.empty()) {
+      const int32_t v = stack.back();
+      stack.pop_back();
+      members.push_back(v);
+      for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+        if (!seen[ci[e]]) { seen[ci[e]] = 1; stack.push_back(ci[e]); }
+    }
+    for (int32_t v : members) out->comp[v] = (int64_t)members.size();
+  }
+  // the kept vertex each tree hangs from, and the top child holding each
+  // removed vertex (parents before children: reverse removal order)
+  for (size_t i = out->order.size(); i-- > 0;) {
+    const int32_t u = out->order[i];
+    const int32_t p = out->parent[u];
+    if (p < 0) {  // root of a tree component: top names it for every vertex of that tree
+      out->top[u] = u;
+    } else if (out->kind[p] == kKept) {
+      out->core[u] = p;
+      out->top[u] = u;
+    } else {
+      out->core[u] = out->core[p];
+      out->top[u] = out->top[p];
+    }
+  }
+  for (int32_t v = 0; v < n; ++v)
+    if (out->kind[v] == kKept) out->omega[v] = (int32_t)(out->sub[v] - 1);
+  out->rp.assign((size_t)n + 1, 0);
+  out->ci.clear();
+  out->ci.reserve((size_t)rp[n]);
+  for (int32_t v = 0; v < n; ++v) {
+    if (out->kind[v] == kKept)
+      for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+        if (out->kind[ci[e]] == kKept) out->ci.push_back(ci[e]);
+    out->rp[v + 1] = (int32_t)out->ci.size();
+  }
+}
+
+void tree_scores(int32_t n, const Pruned& p, const int32_t* src, int64_t k, double* out) {
+  // cnt[v]: requested sources in v's subtree (v's own multiplicity included)
+  std::vector<double> cnt((size_t)n, src ? 0.0 : 1.0);
+  if (src)
+    for (int64_t i = 0; i < k; ++i) cnt[src[i]] += 1.0;
+  // requested sources per component, keyed by a representative: the kept
+  // vertex a tree hangs from, or a tree component's root
+  auto rep = [&](int32_t v) { return p.kind[v] == kKept ? v : (p.core[v] >= 0 ? p.core[v] : p.top[v]); };
+  std::vector<double> in_comp((size_t)n, 0.0);
+  if (src) {
+    // per component: sum over its vertices; kept vertices of one component
+    // are connected through kept vertices only, so label them first
+    std::vector<int32_t> lab((size_t)n, -1), stack;
+    for (int32_t s = 0; s < n; ++s) {
+      if (p.kind[s] != kKept || lab[s] >= 0) continue;
+      lab[s] = s;
+      stack.assign(1, s);
+      while (!stack.empty()) {
+        const int32_t v = stack.back();
+        stack.pop_back();
+        for (int32_t e = p.rp[v]; e < p.rp[v + 1]; ++e)
+          if (lab[p.ci[e]] < 0) { lab[p.ci[e]] = s; stack.push_back(p.ci[e]); }
+      }
+    }
+    for (int64_t i = 0; i < k; ++i) {
+      const int32_t v = src[i];
+      if (p.kind[v] == kIsolated) continue;
+      const int32_t r = rep(v);
+      in_comp[p.kind[r] == kKept ? lab[r] : r] += 1.0;
+    }
+    for (int32_t v = 0; v < n; ++v)
+      if (p.kind[v] == kKept) in_comp[v] = in_comp[lab[v]];
+  }
+  for (int32_t u : p.order) {
+    const int32_t par = p.parent[u];
+    if (par >= 0) cnt[par] += cnt[u];
+  }
+  // sum over the children c of each removed vertex of cnt[c] (N - 1 - sub[c])
+  std::vector<double> child((size_t)n, 0.0);
+  for (int32_t u : p.order) {
+    const int32_t par = p.parent[u];
+    if (par >= 0 && p.kind[par] == kTree) child[par] += cnt[u] * (double)(p.comp[u] - 1 - p.sub[u]);
+  }
+  for (int32_t u : p.order) {
+    const double N = (double)p.comp[u];
+    double total;
+    if (!src) {
+      total = N;  // every vertex of the component is a source
+    } else {
+      total = in_comp[rep(u)];
+    }
+    // sources outside u's subtree reach the sub[u] - 1 vertices below u through it
+    const double outside = total - cnt[u];
+    out[u] += outside * (double)(p.sub[u] - 1) + child[u];
+  }
+}
+
 void map_sources(int32_t n, const int32_t* rp, const Pruned* pr, const int32_t* src, int64_t k,
                  std::vector<Group>* groups, int64_t* credited) {
-  std::vector<double> w((size_t)n, 0.0);
+  std::vector<double> w((size_t)n, 0.0), tsub((size_t)n, 0.0);
   std::vector<int32_t> own((size_t)n, 0);
   std::vector<char> seen((size_t)n, 0);
   std::vector<int32_t> order;
   int64_t cred = 0;
-  auto add = [&](int32_t v, double wt, int32_t ow) {
+  auto add = [&](int32_t v, double wt, int32_t ow, double ts) {
     if (!seen[v]) { seen[v] = 1; order.push_back(v); }
     w[v] += wt;
     own[v] += ow;
+    tsub[v] += ts;
   };
   for (int64_t i = 0; i < k; ++i) {
     const int32_t s = src ? src[i] : (int32_t)i;
     if (rp[s + 1] == rp[s]) continue;  // isolated: no pairs
     ++cred;
-    if (!pr) { add(s, 1.0, 0); continue; }
+    if (!pr) { add(s, 1.0, 0, 0.0); continue; }
     switch (pr->kind[s]) {
-      case kKept: add(s, 1.0, 0); break;
-      case kPendant: add(pr->hub[s], 1.0, 1); break;
+      case kKept: add(s, 1.0, 0, 0.0); break;
+      case kPendant: add(pr->hub[s], 1.0, 1, 1.0); break;
+      case kTree:
+        // served by the sweep of the kept vertex its tree hangs from; a tree
+        // component is scored on the host alone
+        if (pr->core[s] >= 0) add(pr->core[s], 1.0, 1, (double)pr->sub[pr->top[s]]);
+        break;
       default: break;  // ends of 2-vertex components: no inner vertices
     }
   }
   groups->clear();
   groups->reserve(order.size());
-  for (int32_t v : order) groups->push_back(Group{v, w[v], own[v], 0});
+  for (int32_t v : order) groups->push_back(Group{v, w[v], own[v], 0, tsub[v]});
   *credited = cred;
 }
 

@@ -52,7 +52,8 @@ struct PlainArgs {
   double* bc;
   double* delta_out;          // per-vertex delta of this source (trace), or null
   int32_t src;
-  int32_t own;                // pendant sources of src represented by this launch
+  int32_t own;                // folded sources (pendants, tree vertices) represented by this launch
+  double tsub;                // sum over them of the size of src's subtree that holds them
   double weight;              // sources represented by src's sweep
   double alpha;
   int32_t cap_entries, cap_units, cap_parts, cap_multi, cap_levels;
@@ -112,7 +113,8 @@ struct BatchArgs {
   // batch description (device arrays, 64K entries each)
   const int32_t* lane_src;    // source vertex of each lane, -1 = inactive
   const double* lane_w;       // sources represented by the lane's sweep
-  const int32_t* lane_own;    // pendant sources represented (own term)
+  const int32_t* lane_own;    // folded sources represented (own term)
+  const double* lane_tsub;    // sum over them of the size of the lane source's subtree that holds them
   const int8_t* lane_pa;      // derived lanes: partner lanes (same word), -1 if traversed
   const int8_t* lane_pb;
   double* const* slot_bc;     // per-slot score arrays (device), up to 64

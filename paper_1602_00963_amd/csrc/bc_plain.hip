@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
   if (tid == 0) {
     if (!failed && !overflowed && a.own > 0) {
       const double ns = (double)*a.ns;
-      a.bc[a.src] += (double)a.own * (ns - 2.0);
+      a.bc[a.src] += (double)a.own * (ns - 1.0) - a.tsub;  // pendants alone: own * (n_s - 2)
     }
     if (overflowed && !failed) {
       const int32_t k = atomicAdd(a.ovf_count, 1);

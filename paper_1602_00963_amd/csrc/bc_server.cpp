@@ -65,6 +65,7 @@ struct Query {
   bc_status status = BC_OK;
   double submit_ms = 0, start_ms = -1, end_ms = 0;
   int64_t n = 0, m = 0;
+  std::vector<double> tree;   // closed-form scores of tree vertices (iterated reduction), caller order
 };
 
 struct Worker {
@@ -287,8 +288,11 @@ bc_status run_job(bc_server* s, Worker* w, Job& job, std::vector<std::shared_ptr
   }
   if (!complete->empty() && hipStreamSynchronize(w->st) != hipSuccess) st = BC_E_DEVICE;
   if (st == BC_OK)
-    for (auto& q : *complete)
-      if (q->out) scores_to_caller(q->g, q->out);  // the library's vertex order to the caller's
+    for (auto& q : *complete) {
+      if (!q->out) continue;
+      scores_to_caller(q->g, q->out);  // the library's vertex order to the caller's
+      for (size_t v = 0; v < q->tree.size(); ++v) q->out[v] += q->tree[v];
+    }
   return st;
 }
 
@@ -430,6 +434,7 @@ bc_status bc_submit(bc_server* s, bc_graph* g, const int32_t* sources, int64_t k
   if (st != BC_OK) return st;
   q->ws_bytes = (int64_t)graph_ws_bytes(g, r);
   graph_groups(g, r, sources, k, &q->groups, &q->credited);
+  if (r.deg1) tree_scores_caller(g, sources, k, &q->tree);
   std::vector<Buf> frees;
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -439,8 +444,9 @@ bc_status bc_submit(bc_server* s, bc_graph* g, const int32_t* sources, int64_t k
     *ticket = q->ticket;
     s->all[q->ticket] = q;
     if (q->groups.empty()) {
-      // nothing to traverse: the result is all zeros
+      // nothing to traverse: only closed-form scores (tree vertices), else zeros
       if (out) std::fill(out, out + n, 0.0);
+      if (out) for (size_t v = 0; v < q->tree.size(); ++v) out[v] = q->tree[v];
       q->done = true;
       q->end_ms = q->submit_ms;
       return BC_OK;

@@ -181,6 +181,44 @@ def test_degree1_pruning_equals_unpruned(bcm, ctx, opts):
     assert_close(got_s, ref_s, what="pruned subset")
 
 
+def tree_heavy_graph():
+    return gg.disjoint_union(gg.attach_trees(gg.rmat(10, 4, 21), [1, 1, 2, 3, 5, 8, 13, 30, 60, 4, 4, 1, 1, 2], 7),
+                             gg.random_tree(40, 3), gg.path(2), gg.star(6),
+                             gg.attach_trees(gg.cycle(9), [10, 3], 2), gg.path(1))
+
+
+@pytest.mark.parametrize("opts", [dict(mode="plain"), dict(mode="batched", batch=64), dict(mode="batched", batch=256),
+                                  dict(mode="batched", batch=128, deg2=True)],
+                         ids=["plain", "b64", "b256", "b128-deg2"])
+def test_tree_reduction_equals_unpruned(bcm, ctx, opts):
+    """The 1-degree reduction iterated until no degree-1 vertex is left (every
+    hanging tree folded into its attachment vertex, tree components scored in
+    closed form) gives the unpruned scores: all sources, and subsets holding
+    tree vertices at every depth, attachment vertices and tree components."""
+    g = tree_heavy_graph()
+    say("case trees", opts)
+    ref, _ = oracle.bc(g)
+    G = bcm.Graph(ctx, g, prune="trees")
+    assert G.stats()["tree_vertices"] > 150
+    st = G.compute(None, deg1=True, **opts)
+    assert_close(G.scores(), ref, what="trees all")
+    assert st["traversed"] < st["sources"] - 150
+    rng = np.random.default_rng(3)
+    for t in range(3):
+        S = rng.integers(0, g.n, size=int(rng.integers(50, 600))).astype(np.int32)
+        G.reset()
+        G.compute(S, deg1=True, **opts)
+        ref_s, _ = oracle.bc(g, S)
+        assert_close(G.scores(), ref_s, what=f"trees subset {t}")
+    # sources only inside tree components: no sweep at all
+    S = np.arange(g.n - 50, g.n - 10, dtype=np.int32)
+    G.reset()
+    G.compute(S, deg1=True, **opts)
+    ref_s, _ = oracle.bc(g, S)
+    assert_close(G.scores(), ref_s, what="tree components")
+    G.close()
+
+
 @pytest.mark.parametrize("batch", [64, 256])
 def test_degree2_derivation_equals_unpruned(bcm, ctx, batch):
     """2-degree vertices whose neighbours are sources of the same batch get

@@ -205,13 +205,16 @@ def test_batches_run_concurrently(bcm, ctx):
         G.close()
 
 
-def test_server_deg1_subsets(bcm, ctx):
-    """Queries on a pruned graph use the 1-degree reduction for their source
-    subsets (pendants, hubs, ends of 2-vertex components among them); each
-    result equals the unpruned oracle on the same subset, alone and mixed."""
-    g = gg.disjoint_union(gg.rmat_with_pendants(11, 8, 3, 0.3, 33), gg.star(9), gg.path(2), gg.path(3))
-    G = bcm.Graph(ctx, g, prune=True)
-    assert G.stats()["pendants"] > 100
+@pytest.mark.parametrize("prune", [True, "trees"], ids=["one-round", "iterated"])
+def test_server_deg1_subsets(bcm, ctx, prune):
+    """Queries on a pruned graph use the 1-degree reduction (one round, or
+    iterated until no tree is left) for their source subsets (pendants, tree
+    vertices, hubs, ends of 2-vertex components among them); each result
+    equals the unpruned oracle on the same subset, alone and mixed."""
+    g = gg.disjoint_union(gg.attach_trees(gg.rmat_with_pendants(11, 8, 3, 0.3, 33), [5, 9, 2, 17], 4),
+                          gg.star(9), gg.path(2), gg.path(3))
+    G = bcm.Graph(ctx, g, prune=prune)
+    assert G.stats()["pendants" if prune is True else "tree_vertices"] > 100
     rng = np.random.default_rng(9)
     every = np.arange(g.n, dtype=np.int32)
     subsets = [gg.sample(every, int(rng.integers(50, 900)), 60 + i) for i in range(6)]
