@@ -250,6 +250,19 @@ bc_status bc_prune_deg1_host(int32_t n, const int32_t* row_ptr, const int32_t* c
 bc_status bc_prune_trees_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* sources,
                               int64_t k, int32_t* omega, int32_t* kind, double* scores, int64_t* res_nnz);
 
+/*
+ * Heuristics coverage for all sources (the count the paper's heuristics
+ * table reports), host only: with load_flags (BC_LOAD_PRUNE_DEG1 or
+ * BC_LOAD_PRUNE_TREES) and heuristics (BC_H_DEG1, BC_H_DEG2) as bc_compute
+ * would use them (1-degree reduction of Sec. 3.4.1; 2-degree derivation of
+ * Sec. 3.4.2 with the library's greedy selection in breadth-first order from
+ * the highest-degree vertex).  out[5]: non-isolated sources, sweeps
+ * traversed, sources served by the 1-degree reduction, sources derived by
+ * the 2-degree heuristic, degree-2 vertices among the traversal sources.
+ */
+bc_status bc_coverage_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t load_flags,
+                           uint32_t heuristics, int64_t* out);
+
 /* ------------------------------------------------------------------ serving */
 
 typedef struct bc_server_config {

@@ -29,7 +29,7 @@ EXPORTED = ["bc_context_create", "bc_context_destroy", "bc_graph_load", "bc_grap
             "bc_workspace_size", "bc_compute", "bc_scores", "bc_scores_reset", "bc_trace", "bc_validate_csr",
             "bc_prune_deg1_host", "bc_server_create", "bc_server_destroy", "bc_submit", "bc_wait",
             "bc_status_string", "bc_last_error", "bc_autotune", "bc_compute_noalloc",
-            "bc_server_stats_get", "bc_prune_trees_host"]
+            "bc_server_stats_get", "bc_prune_trees_host", "bc_coverage_host"]
 
 
 class GraphStats(ctypes.Structure):
@@ -116,6 +116,7 @@ def lib():
             "bc_compute_noalloc": [vp, vp, i64, vp, vp, vp],
             "bc_server_stats_get": [vp, vp],
             "bc_prune_trees_host": [i32, vp, vp, vp, i64, vp, vp, vp, vp],
+            "bc_coverage_host": [i32, vp, vp, u32, u32, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -177,6 +178,18 @@ def prune_trees_host(n: int, row_ptr, col_idx, sources=None) -> dict:
     _check(lib().bc_prune_trees_host(n, _p(rp), _p(ci), _p(src), 0 if src is None else len(src), _p(omega),
                                      _p(kind), _p(sc), ctypes.byref(rnnz)), "bc_prune_trees_host")
     return {"omega": omega, "kind": kind, "scores": sc, "residual_nnz": rnnz.value}
+
+
+def coverage_host(n: int, row_ptr, col_idx, prune=False, deg1=False, deg2=False) -> dict:
+    """Heuristics coverage over all sources (host only): sources, sweeps
+    traversed, sources served by the 1-degree reduction, sources derived by
+    the 2-degree heuristic, degree-2 traversal sources."""
+    rp, ci = _i32(row_ptr), _i32(col_idx)
+    lf = LOAD_PRUNE_TREES if prune == "trees" else (LOAD_PRUNE_DEG1 if prune else 0)
+    out = np.zeros(5, np.int64)
+    _check(lib().bc_coverage_host(n, _p(rp), _p(ci), lf, (H_DEG1 if deg1 else 0) | (H_DEG2 if deg2 else 0),
+                                  _p(out)), "bc_coverage_host")
+    return dict(zip(["sources", "traversed", "one_degree", "two_degree", "deg2_candidates"], (int(x) for x in out)))
 
 
 class Context:

@@ -129,7 +129,8 @@ struct BatchWs {
   uint32_t* lane_ovf;
   unsigned long long *lane_ns, *stats, *fulledges;
   GridBar* bar;
-  size_t mask_bytes;   // vis + fm, cleared per call
+  size_t mask_bytes;   // vis + fm + dla + dlb, cleared per call
+  uint64_t *dla, *dlb;
   int32_t cap_pairs;   // (word, slot) pair arrays
   char* tables;        // kTableBatches lane tables
   size_t table_bytes;  // bytes of one table
@@ -140,12 +141,12 @@ struct BatchWs {
 
 // One batch's lane table: lane_src[B], lane_own[B], l0[B] (int32), lane_w[B],
 // lane_tsub[B] (double), lane_pair[B] (int16), lane_pa[B], lane_pb[B], lane_slot[B]
-// (int8), pair_slot[kMaxPairs] (int8), then 8-aligned edge_lanes[16]
+// (int8), pair_slot[kMaxPairs] (int8), then 8-aligned edge_lanes[16], derived_lanes[16]
 // (uint64) and slot_bc[64] (device pointers).
 constexpr int kMaxSlots = 64;
 constexpr int kMaxPairs = kMaxWords + kMaxSlots;
 size_t table_bytes(int B) {
-  return align_up((size_t)B * (4 + 4 + 4 + 8 + 8 + 2 + 1 + 1 + 1) + kMaxPairs + 8 + 8 * kMaxWords + 8 * kMaxSlots, 256);
+  return align_up((size_t)B * (4 + 4 + 4 + 8 + 8 + 2 + 1 + 1 + 1) + kMaxPairs + 8 + 16 * kMaxWords + 8 * kMaxSlots, 256);
 }
 
 // Lanes are packed slot by slot, so the slots met along the words are
@@ -161,9 +162,11 @@ size_t batch_layout(int64_t n, int64_t nnz, int B, int cap_factor, int max_slots
   t.lv = with_lv ? c.take<int32_t>((size_t)n * B) : nullptr;  // per-lane levels: traces only
   t.sig = c.take<uint64_t>((size_t)n * B);
   t.se = c.take<int32_t>((size_t)n * B);
-  t.vis = c.take<uint64_t>((size_t)n * K * 5);  // vis then the four level-mask arrays
+  t.vis = c.take<uint64_t>((size_t)n * K * 7);  // vis, the four level-mask arrays, dla, dlb
   t.fm = t.vis ? t.vis + (size_t)n * K : nullptr;
-  t.mask_bytes = sizeof(uint64_t) * (size_t)n * K * 5;
+  t.dla = t.vis ? t.vis + (size_t)n * K * 5 : nullptr;
+  t.dlb = t.vis ? t.vis + (size_t)n * K * 6 : nullptr;
+  t.mask_bytes = sizeof(uint64_t) * (size_t)n * K * 7;
   t.Q = c.take<uint64_t>(t.caps.entries);
   t.U = c.take<BUnit>(t.caps.units);
   t.qoff = c.take<int32_t>(n + 3);
@@ -418,6 +421,36 @@ bc_status bc_prune_trees_host(int32_t n, const int32_t* row_ptr, const int32_t* 
   return BC_OK;
 }
 
+bc_status bc_coverage_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t load_flags,
+                           uint32_t heuristics, int64_t* out) {
+  if (!row_ptr || !col_idx || n < 0 || !out) return fail(BC_E_INVALID_ARG, "bad arguments");
+  const bool prune = (load_flags & (BC_LOAD_PRUNE_DEG1 | BC_LOAD_PRUNE_TREES)) && (heuristics & BC_H_DEG1);
+  Pruned p;
+  if (prune) {
+    if (load_flags & BC_LOAD_PRUNE_TREES) prune_trees(n, row_ptr, col_idx, &p);
+    else prune_deg1(n, row_ptr, col_idx, &p);
+  }
+  std::vector<Group> groups;
+  int64_t credited = 0;
+  map_sources(n, row_ptr, prune ? &p : nullptr, nullptr, n, &groups, &credited);
+  const int32_t* trp = prune ? p.rp.data() : row_ptr;
+  const int32_t* tci = prune ? p.ci.data() : col_idx;
+  int64_t cand = 0;
+  for (const auto& gr : groups) cand += trp[gr.v + 1] - trp[gr.v] == 2;
+  std::vector<Triple> triples;
+  if (heuristics & BC_H_DEG2) {
+    const std::vector<int32_t> rank = locality_rank(n, row_ptr, col_idx);
+    order_groups(rank, groups);
+    choose_deg2(n, trp, tci, groups, &triples);
+  }
+  out[0] = credited;                                              // non-isolated sources
+  out[1] = (int64_t)groups.size() - (int64_t)triples.size();      // sweeps traversed
+  out[2] = credited - (int64_t)groups.size();                     // served by the 1-degree reduction
+  out[3] = (int64_t)triples.size();                               // derived (2-degree)
+  out[4] = cand;                                                  // degree-2 vertices among the sweeps
+  return BC_OK;
+}
+
 bc_status bc_graph_load(bc_context* ctx, int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
                         int64_t nnz, uint32_t flags, bc_graph** out) {
   if (!ctx || !out || n <= 0 || !row_ptr || (nnz > 0 && !col_idx)) return fail(BC_E_INVALID_ARG, "bad arguments");
@@ -610,30 +643,60 @@ struct Packing {
 
 static void pack_lanes(const std::vector<Group>& groups, const std::vector<Triple>& triples, int B, Packing* p) {
   p->B = B;
-  std::vector<char> in_triple(groups.size(), 0);
-  for (const auto& t : triples) in_triple[t.a] = in_triple[t.b] = in_triple[t.c] = 1;
-  std::vector<int32_t> lanes;
+  const size_t G = groups.size();
+  // clusters: derived vertices with their partners, joined through shared
+  // partners (each fits one 64-lane word by construction)
+  std::vector<int32_t> uf(G);
+  for (size_t i = 0; i < G; ++i) uf[i] = (int32_t)i;
+  auto find = [&](int32_t x) {
+    while (uf[x] != x) x = uf[x] = uf[uf[x]];
+    return x;
+  };
+  std::vector<char> in_cluster(G, 0);
+  std::vector<std::pair<int32_t, int32_t>> partners(G, {-1, -1});
+  for (const auto& t : triples) {
+    in_cluster[t.a] = in_cluster[t.b] = in_cluster[t.c] = 1;
+    partners[t.c] = {t.a, t.b};
+    uf[find(t.a)] = find(t.c);
+    uf[find(t.b)] = find(t.c);
+  }
+  std::vector<std::vector<int32_t>> members(G);
+  std::vector<int32_t> roots;
+  for (size_t i = 0; i < G; ++i) {
+    if (!in_cluster[i]) continue;
+    const int32_t r = find((int32_t)i);
+    if (members[r].empty()) roots.push_back(r);
+    members[r].push_back((int32_t)i);
+  }
+  std::vector<int32_t> lanes, pos(G, -1);
   std::vector<int8_t> pa, pb;
-  auto pad_to_word = [&](int need) {
+  auto pad_to_word = [&](size_t need) {
     const size_t used = lanes.size() % 64;
     if (used + need > 64) {
       while (lanes.size() % 64) { lanes.push_back(-1); pa.push_back(-1); pb.push_back(-1); }
     }
   };
-  // slot by slot (a triple's members share one slot): its triples, then its other groups
+  // slot by slot (a cluster's members share one slot): its clusters, then its other groups
   int nslot = 1;
   for (const auto& gr : groups) nslot = std::max(nslot, gr.slot + 1);
   for (int sl = 0; sl < nslot; ++sl) {
-    for (const auto& t : triples) {
-      if (groups[t.c].slot != sl) continue;
-      pad_to_word(3);
-      const int base = (int)(lanes.size() % 64);
-      lanes.push_back(t.a); pa.push_back(-1); pb.push_back(-1);
-      lanes.push_back(t.b); pa.push_back(-1); pb.push_back(-1);
-      lanes.push_back(t.c); pa.push_back((int8_t)base); pb.push_back((int8_t)(base + 1));
+    for (int32_t r : roots) {
+      if (groups[r].slot != sl) continue;
+      pad_to_word(members[r].size());
+      for (int32_t m : members[r]) {  // partners first, then the derived lanes that point at them
+        if (partners[m].first >= 0) continue;
+        pos[m] = (int32_t)(lanes.size() % 64);
+        lanes.push_back(m); pa.push_back(-1); pb.push_back(-1);
+      }
+      for (int32_t m : members[r]) {
+        if (partners[m].first < 0) continue;
+        lanes.push_back(m);
+        pa.push_back((int8_t)pos[partners[m].first]);
+        pb.push_back((int8_t)pos[partners[m].second]);
+      }
     }
-    for (size_t i = 0; i < groups.size(); ++i) {
-      if (in_triple[i] || groups[i].slot != sl) continue;
+    for (size_t i = 0; i < G; ++i) {
+      if (in_cluster[i] || groups[i].slot != sl) continue;
       lanes.push_back((int32_t)i); pa.push_back(-1); pb.push_back(-1);
     }
   }
@@ -650,7 +713,7 @@ struct TablePtrs {
   double *lane_w, *lane_tsub;
   int16_t* pair;
   int8_t *pa, *pb, *slot, *pair_slot;
-  uint64_t* el;
+  uint64_t *el, *dl;
   double** slot_bc;
 };
 
@@ -667,7 +730,8 @@ static TablePtrs table_at(char* t, int B) {
   p.slot = p.pb + B;
   p.pair_slot = p.slot + B;
   p.el = (uint64_t*)(((uintptr_t)(p.pair_slot + kMaxPairs) + 7) & ~(uintptr_t)7);
-  p.slot_bc = (double**)(p.el + kMaxWords);
+  p.dl = p.el + kMaxWords;
+  p.slot_bc = (double**)(p.dl + kMaxWords);
   return p;
 }
 
@@ -682,7 +746,7 @@ struct TableInfo {
 static TableInfo fill_table(char* dst, const Packing& pk, int64_t b, const std::vector<Group>& groups, int B,
                             double* const* slot_ptrs, int nslots) {
   TablePtrs t = table_at(dst, B);
-  for (int k = 0; k < kMaxWords; ++k) t.el[k] = 0;
+  for (int k = 0; k < kMaxWords; ++k) t.el[k] = t.dl[k] = 0;
   for (int s = 0; s < kMaxSlots; ++s) t.slot_bc[s] = s < nslots ? slot_ptrs[s] : nullptr;
   for (int p = 0; p < kMaxPairs; ++p) t.pair_slot[p] = 0;
   TableInfo info{0, 0, false};
@@ -708,8 +772,12 @@ static TableInfo fill_table(char* dst, const Packing& pk, int64_t b, const std::
     }
     t.pair[j] = (int16_t)(info.npairs - 1);
     distinct.push_back(groups[gi].v);
-    if (t.pa[j] < 0) t.el[j >> 6] |= 1ull << (j & 63);
-    else info.derived = true;
+    if (t.pa[j] < 0) {
+      t.el[j >> 6] |= 1ull << (j & 63);
+    } else {
+      t.dl[j >> 6] |= 1ull << (j & 63);
+      info.derived = true;
+    }
   }
   std::sort(distinct.begin(), distinct.end());
   distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
@@ -727,6 +795,7 @@ static void table_ptrs(char* dev, int B, BatchArgs* a) {
   a->lane_pa = t.pa;
   a->lane_pb = t.pb;
   a->edge_lanes = t.el;
+  a->derived_lanes = t.dl;
   a->slot_bc = t.slot_bc;
   a->lane_pair = t.pair;
   a->pair_slot = t.pair_slot;
@@ -811,6 +880,8 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   HIPCHK(hipMemsetAsync(w.pair_bc, 0, sizeof(double) * (size_t)w.cap_pairs * g->n, st));
   Packing pk;
   pack_lanes(groups, triples, r.B, &pk);
+  // a trace call owns trace rows for one launch of B lanes only
+  if (tr && pk.nbatches > 1) return fail(BC_E_INVALID_ARG, "a trace call must pack into one launch");
   if (trace_lane_vertex) trace_lane_vertex->assign(pk.lane_group.begin(), pk.lane_group.end());
   char* stage = nullptr;
   bc_status s = ex->tables(w.table_bytes * kTableBatches, &stage);
@@ -831,6 +902,8 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   a.se = w.se;
   a.vis = w.vis;
   a.fm = w.fm;
+  a.dla = w.dla;
+  a.dlb = w.dlb;
   a.Q = w.Q;
   a.U = w.U;
   a.qoff = w.qoff;
@@ -1072,7 +1145,12 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
     std::call_once(g->rank_once, [g] { g->rank = locality_rank(g->n, g->h_rp.data(), g->h_ci.data()); });
     order_groups(g->rank, groups);
   }
-  if (r.deg2) choose_deg2(g->n, tg.h_rp, tg.h_ci, groups, &triples);
+  // AUTO counts probe one word of sources first (below); 2-degree
+  // derivation is chosen among the other sources
+  const bool probe = r.mode == BC_MODE_BATCHED && r.sigma_mode == BC_SIGMA_AUTO && groups.size() > (size_t)r.B;
+  std::vector<Group> rest;
+  if (probe) rest.assign(groups.begin() + 64, groups.end());
+  if (r.deg2) choose_deg2(g->n, tg.h_rp, tg.h_ci, probe ? rest : groups, &triples);
   bc_run_stats rs{};
   for (int i = 0; i < 8; ++i) rs.first_overflow[i] = -1;
   rs.sources = credited;
@@ -1082,9 +1160,7 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
   bool ext0 = r.sigma_mode == BC_SIGMA_EXTENDED;
   CallOut co;
   bc_status s = BC_OK;
-  std::vector<Group> rest;
-  if (r.mode == BC_MODE_BATCHED && r.sigma_mode == BC_SIGMA_AUTO && triples.empty() &&
-      groups.size() > (size_t)r.B) {
+  if (probe) {
     // probe: one word of sources in exact form (lists at their worst-case
     // size); if most of them wrap (long diameters), the other batches go
     // straight to the extended form, and - when the library owns the
@@ -1096,7 +1172,6 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
     rp.K = 1;
     rp.cap_factor = 64;
     std::vector<Group> head(groups.begin(), groups.begin() + 64);
-    rest.assign(groups.begin() + 64, groups.end());
     s = run_groups(g, workspace ? r : rp, false, tg, head, {}, workspace, ws_bytes, st, slots, nslots, ex, &co);
     if (s != BC_OK) return s;
     if (2 * co.ovf.size() > head.size()) {
@@ -1110,7 +1185,7 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
       }
     }
     CallOut c2;
-    s = run_groups(g, rr, ext0, tg, rest, {}, workspace, ws_bytes, st, slots, nslots, ex, &c2);
+    s = run_groups(g, rr, ext0, tg, rest, triples, workspace, ws_bytes, st, slots, nslots, ex, &c2);
     if (s != BC_OK) return s;
     co.merge(c2);
     co.ovf.insert(co.ovf.end(), c2.ovf.begin(), c2.ovf.end());
@@ -1353,7 +1428,8 @@ static bc_status trace_internal(bc_graph* g, const int32_t* sources, int64_t k, 
   Resolved r;
   bc_status s = resolve(g, opts, &r);
   if (s != BC_OK) return s;
-  if (r.deg1 || r.deg2) return fail(BC_E_INVALID_ARG, "traces run on the unpruned graph without heuristics");
+  if (r.deg1 || (r.deg2 && r.mode != BC_MODE_BATCHED))
+    return fail(BC_E_INVALID_ARG, "traces run on the unpruned graph (2-degree derivation: batched only)");
   r.trace = true;
   for (int64_t i = 0; i < k; ++i)
     if (sources[i] < 0 || sources[i] >= g->n) return fail(BC_E_INVALID_ARG, "source id out of range");
@@ -1417,13 +1493,28 @@ static bc_status trace_internal(bc_graph* g, const int32_t* sources, int64_t k, 
       hipMalloc((void**)&dbc, sizeof(double) * n) != hipSuccess)
     res = fail(BC_E_OUT_OF_MEMORY, "trace buffers");
   std::vector<int32_t> lv((size_t)n * B);
-  std::vector<uint64_t> vis((size_t)n * r.K);
+  std::vector<uint64_t> vis((size_t)n * r.K), dla((size_t)n * r.K), dlb((size_t)n * r.K);
   std::vector<double> hd(cells), hm;
   std::vector<uint64_t> hs;
   std::vector<int32_t> he;
   double* slots[1] = {dbc};
-  for (int64_t b0 = 0; b0 < k && res == BC_OK; b0 += B) {
-    const int64_t nb = std::min<int64_t>(B, k - b0);
+  for (int64_t b0 = 0, nb = 0; b0 < k && res == BC_OK; b0 += nb) {
+    nb = std::min<int64_t>(B, k - b0);
+    if (r.deg2) {
+      // triples share a word, so padding can push B sources past one launch:
+      // take fewer sources until their lanes pack into one
+      while (nb > 1) {
+        std::vector<Group> probe;
+        for (int64_t i = 0; i < nb; ++i) probe.push_back(Group{sources[b0 + i], 1.0, 0, 0});
+        std::vector<Triple> tp;
+        choose_deg2(g->n, tg.h_rp, tg.h_ci, probe, &tp);
+        Packing pk;
+        pack_lanes(probe, tp, B, &pk);
+        if (pk.nbatches <= 1) break;
+        nb -= 8;
+        if (nb < 1) nb = 1;
+      }
+    }
     for (int pass = 0; pass < 2 && res == BC_OK; ++pass) {
       const bool ext = ext_only || pass == 1;
       std::vector<Group> run;
@@ -1435,14 +1526,26 @@ static bc_status trace_internal(bc_graph* g, const int32_t* sources, int64_t k, 
       }
       if (run.empty()) break;
       if (hipMemset(dd, 0, sizeof(double) * cells) != hipSuccess) { res = fail(BC_E_DEVICE, "memset"); break; }
+      // 2-degree derivation on the first pass (reruns of wrapped sources traverse)
+      std::vector<Triple> triples;
+      if (r.deg2 && pass == 0) choose_deg2(g->n, tg.h_rp, tg.h_ci, run, &triples);
+      std::vector<char> derived(run.size(), 0);
+      std::vector<std::pair<int32_t, int32_t>> partners(run.size(), {-1, -1});
+      for (const auto& t : triples) {
+        derived[t.c] = 1;
+        partners[t.c] = {t.a, t.b};
+      }
       TraceDev tdv{dd, dsg, (double*)dsg, dse, dbc};
       CallOut co;
       std::vector<int32_t> lanes;
-      res = run_batched(g, r, ext, tg, run, {}, ws, B, st, slots, 1, &tdv, &g->exec, &co, &lanes);
+      res = run_batched(g, r, ext, tg, run, triples, ws, B, st, slots, 1, &tdv, &g->exec, &co, &lanes);
       if (res != BC_OK) break;
       if (!co.fail.empty()) { res = fail(BC_E_CAPACITY, "capacity exceeded"); break; }
       if (hipMemcpy(lv.data(), w.lv, sizeof(int32_t) * lv.size(), hipMemcpyDeviceToHost) != hipSuccess ||
           hipMemcpy(vis.data(), w.vis, sizeof(uint64_t) * vis.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+          (!triples.empty() &&
+           (hipMemcpy(dla.data(), w.dla, sizeof(uint64_t) * dla.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(dlb.data(), w.dlb, sizeof(uint64_t) * dlb.size(), hipMemcpyDeviceToHost) != hipSuccess)) ||
           hipMemcpy(hd.data(), dd, sizeof(double) * cells, hipMemcpyDeviceToHost) != hipSuccess) {
         res = fail(BC_E_DEVICE, "trace copy");
         break;
@@ -1460,16 +1563,43 @@ static bc_status trace_internal(bc_graph* g, const int32_t* sources, int64_t k, 
       for (int32_t v : co.ovf)
         for (size_t gi = 0; gi < run.size(); ++gi)
           if (run[gi].v == v) wrapped[gi] = 1;
+      std::vector<int32_t> lane_of(run.size(), -1);
+      for (int j = 0; j < B; ++j)
+        if (lanes[j] >= 0) lane_of[lanes[j]] = j;
       for (int j = 0; j < B; ++j) {
         const int32_t gi = lanes[j];
         if (gi < 0) continue;
         const int64_t rw = row[gi];
         if (pass == 0 && !ext) ovf_row[rw] = wrapped[gi];
+        // a derived source keeps no levels of its own: it reaches v where the
+        // kernel recorded a partner's arrival (dla / dlb), at 1 + the smaller
+        // of the partners' levels; its own vertex is level 0 with one path
+        const int ja = derived[gi] ? lane_of[partners[gi].first] : -1;
+        const int jb = derived[gi] ? lane_of[partners[gi].second] : -1;
         for (int64_t v = 0; v < n; ++v) {
-          const bool reached = (vis[(size_t)v * r.K + (j >> 6)] >> (j & 63)) & 1ull;
+          const size_t vk = (size_t)v * r.K + (j >> 6);
+          bool reached = (vis[vk] >> (j & 63)) & 1ull;
+          int32_t lvl = reached ? lv[(size_t)v * B + j] : -1;
+          const bool self = derived[gi] && v == run[gi].v;
+          if (derived[gi]) {
+            reached = self || (((dla[vk] | dlb[vk]) >> (j & 63)) & 1ull);
+            lvl = -1;
+            if (self) {
+              lvl = 0;
+            } else if (reached) {
+              const bool ra = (vis[(size_t)v * r.K + (ja >> 6)] >> (ja & 63)) & 1ull;
+              const bool rb = (vis[(size_t)v * r.K + (jb >> 6)] >> (jb & 63)) & 1ull;
+              const int32_t la = ra ? lv[(size_t)v * B + ja] : INT32_MAX, lb = rb ? lv[(size_t)v * B + jb] : INT32_MAX;
+              lvl = 1 + std::min(la, lb);
+            }
+          }
           const size_t c = (size_t)j * n + v;
-          if (d) d[rw * n + v] = reached ? lv[(size_t)v * B + j] : -1;
-          if (ext) {
+          if (d) d[rw * n + v] = lvl;
+          if (self) {
+            if (sigma) sigma[rw * n + v] = ext ? 0 : 1;
+            if (sigma_mant) sigma_mant[rw * n + v] = 1.0;
+            if (sigma_exp) sigma_exp[rw * n + v] = 0;
+          } else if (ext) {
             if (sigma) sigma[rw * n + v] = 0;
             if (sigma_mant) sigma_mant[rw * n + v] = hm[c];
             if (sigma_exp) sigma_exp[rw * n + v] = he[c];

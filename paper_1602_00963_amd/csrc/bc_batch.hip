@@ -388,29 +388,53 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
       }
     }
   }
-  // finalise word k at w: counts, levels, visited mask; derived lanes by Eq. (6)
-  if ((nbm >> lane) & 1ull) {
-    const size_t idx = (size_t)w * B + 64 * k + lane;
-    if (!((em >> lane) & 1ull)) {
-      const int pa = a.lane_pa[64 * k + lane], pb = a.lane_pb[64 * k + lane];
-      const uint64_t cw = par[wk];
-      const size_t ia = (size_t)w * B + 64 * k + pa, ib = (size_t)w * B + 64 * k + pb;
-      if (EXT) {
-        Ext t = ext_zero();
-        if ((cw >> pa) & 1ull) t = ext_add(t, Ext{a.sm[ia], a.se[ia]});
-        if ((cw >> pb) & 1ull) t = ext_add(t, Ext{a.sm[ib], a.se[ib]});
-        x = t;
-      } else {
-        uint64_t t = 0;
-        if ((cw >> pa) & 1ull) t += a.sig[ia];
-        if ((cw >> pb) & 1ull) {
-          const uint64_t y = a.sig[ib];
-          if (t + y < t) wrap = true;
-          t += y;
-        }
-        s = t;
+  // derived lanes (2-degree vertex c with partner lanes a, b; Lemma 1,
+  // Eq. (6)): the first partner to reach w fixes d_c(w) = 1 + min(d_a, d_b)
+  // and sigma_c(w) = the partners' counts on that level; dla / dlb record
+  // whether d_a(w) <= d_b(w) / d_b(w) <= d_a(w) (both at a tie), which the
+  // fused backward sweep uses to merge the two partners' frontiers
+  if (a.derived_lanes[k] != 0) {
+    const int pa = a.lane_pa[64 * k + lane], pb = a.lane_pb[64 * k + lane];
+    const uint64_t before = a.vis[wk];  // lanes of the word that reached w on earlier levels
+    bool la = false, lb = false;
+    if (pa >= 0 && a.lane_src[64 * k + lane] != w) {
+      la = ((nbm >> pa) & 1ull) && !((before >> pb) & 1ull);
+      lb = ((nbm >> pb) & 1ull) && !((before >> pa) & 1ull);
+    }
+    const int qa = pa >= 0 ? pa : lane, qb = pb >= 0 ? pb : lane;
+    const size_t idc = (size_t)w * B + 64 * k + lane;
+    if (EXT) {
+      const Ext xa{__shfl(x.m, qa, kWave), __shfl(x.e, qa, kWave)};
+      const Ext xb{__shfl(x.m, qb, kWave), __shfl(x.e, qb, kWave)};
+      Ext t = ext_zero();
+      if (la) t = ext_add(t, xa);
+      if (lb) t = ext_add(t, xb);
+      if (la || lb) {
+        const Ext z = ext_norm(t);
+        a.sm[idc] = z.m;
+        a.se[idc] = z.e;
+      }
+    } else {
+      const uint64_t sa = __shfl(s, qa, kWave), sb = __shfl(s, qb, kWave);
+      const bool wa = __shfl((int)wrap, qa, kWave) != 0, wb = __shfl((int)wrap, qb, kWave) != 0;
+      uint64_t t = la ? sa : 0ull;
+      bool wc = (la && wa) || (lb && wb);
+      if (lb) {
+        if (t + sb < t) wc = true;
+        t += sb;
+      }
+      if (la || lb) {
+        a.sig[idc] = t;
+        if (wc) atomicOr(&a.lane_ovf[64 * k + lane], 1u);
       }
     }
+    const uint64_t LA = ballot(la), LB = ballot(lb);
+    if (lane == 0 && LA) atomicOr((unsigned long long*)&a.dla[wk], (unsigned long long)LA);
+    if (lane == 0 && LB) atomicOr((unsigned long long*)&a.dlb[wk], (unsigned long long)LB);
+  }
+  // finalise word k at w: counts, levels, visited mask
+  if ((nbm >> lane) & 1ull) {
+    const size_t idx = (size_t)w * B + 64 * k + lane;
     if (EXT) {
       const Ext z = ext_norm(x);
       a.sm[idx] = z.m;
@@ -557,23 +581,57 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const BUnit& u
   // issued together: the first chunk's neighbours, the unit's lanes and
   // levels, and what the lanes' dependencies will need
   const int32_t vl0 = beg + lane < end ? ci[beg + lane] : 0;
-  const uint64_t om = a.emask[un.e] & ~st.sX[k];  // the word's lanes on level lb at w
+  // the word's edge lanes on level lb at w (level 0: the lanes whose source is w)
+  const uint64_t at = lb > 0 ? a.emask[un.e]
+                             : ballot(a.lane_src[64 * k + lane] == w && a.lane_pa[64 * k + lane] < 0);
+  const uint64_t om = lb > 0 ? at & ~st.sX[k] : 0ull;  // edge lanes accumulating here (none at a source)
   const double sw = EXT ? a.sm[idx] : (double)a.sig[idx];
   const double lw = a.lane_w[64 * k + lane];
   const int pr = a.lane_pair[64 * k + lane];
-  if (c == 0 && lane == 0) own[wk] = om;
+  // Dynamic merging of frontiers (fused 2-degree backward): a derived lane c
+  // accumulates delta_c(w) here, at level lb = d_c(w) - 1, when its partner
+  // lane a sits on w at this level and d_a(w) <= d_b(w) (a-pass), or b does
+  // and d_b(w) < d_a(w) (b-pass).  Its successors v are those of that
+  // partner (d_x(v) = lb + 1) with d_x(v) <= d_y(v) (the dla / dlb masks);
+  // c's own vertex is never one (dla, dlb stay clear there).
+  const uint64_t DL = a.derived_lanes[k] & ~st.sX[k];
+  uint64_t dm = 0, dA = 0, PL = 0;
+  int pa = 0, pb = 0;
+  if (DL) {
+    const uint64_t LAw = a.dla[wk], LBw = a.dlb[wk];
+    pa = a.lane_pa[64 * k + lane];
+    pb = a.lane_pb[64 * k + lane];
+    bool ia = false, ib = false;
+    if ((DL >> lane) & 1ull) {
+      ia = ((at >> pa) & 1ull) && ((LAw >> lane) & 1ull);
+      ib = ((at >> pb) & 1ull) && ((LBw >> lane) & 1ull) && !((LAw >> lane) & 1ull);
+    }
+    dm = ballot(ia || ib);
+    dA = ballot(ia);
+    PL = wave_or_u64((ia || ib) ? ((1ull << pa) | (1ull << pb)) : 0ull);
+  }
+  const uint64_t om2 = om | dm;
+  const bool mine = (dm >> lane) & 1ull, apass = (dA >> lane) & 1ull;
+  if (c == 0 && lane == 0 && lb > 0) own[wk] = om;
   double acc = 0.0;
-  if (om && lb < depth) {
-    const int32_t ew = (EXT && ((om >> lane) & 1ull)) ? a.se[idx] : 0;
+  if (om2 && lb < depth) {
+    const int32_t ew = (EXT && ((om2 >> lane) & 1ull)) ? a.se[idx] : 0;
     for (int32_t off0 = beg; off0 < end; off0 += kWave) {
       const int32_t off = off0 + lane;
       int32_t vl = 0;
-      uint64_t ml = 0;
+      uint64_t ml = 0, cm = 0, lav = 0, lbv = 0;
+      bool dc = false;
       if (off < end) {
         vl = off0 == beg ? vl0 : ci[off];
-        ml = cmv[(size_t)vl * K + k] & om;
+        cm = cmv[(size_t)vl * K + k];
+        ml = cm & om;
+        if (dm && (cm & PL)) {
+          lav = a.dla[(size_t)vl * K + k];
+          lbv = a.dlb[(size_t)vl * K + k];
+          dc = ((lav | lbv) & dm) != 0;
+        }
       }
-      uint64_t act = ballot(ml != 0);
+      uint64_t act = ballot(ml != 0 || dc);
       while (act) {
         int ti[G];
 #pragma unroll
@@ -589,7 +647,14 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const BUnit& u
             const int32_t v = rl32(vl, ti[i]);
             const uint64_t mv = rl64(ml, ti[i]);
             const size_t row = (size_t)v * B + 64 * k;  // uniform base, lane offset
-            if ((mv >> lane) & 1ull) {
+            bool take = (mv >> lane) & 1ull;
+            if (dm) {
+              const uint64_t cv = rl64(cm, ti[i]), av = rl64(lav, ti[i]), bv = rl64(lbv, ti[i]);
+              if (mine)
+                take = apass ? (((cv >> pa) & 1ull) && ((av >> lane) & 1ull))
+                             : (((cv >> pb) & 1ull) && ((bv >> lane) & 1ull));
+            }
+            if (take) {
               ys[i] = (psi + row)[lane];
               if (EXT) ys[i] = ldexp(ys[i], ew - (a.se + row)[lane]);
             }
@@ -607,22 +672,23 @@ __device__ __forceinline__ void backward_unit(const BatchArgs& a, const BUnit& u
     int32_t prev = 0;
     if (lane == 0) prev = atomicAdd(&a.arrive[un.e], 1);
     prev = __shfl(prev, 0, kWave);
-    if (prev != 2 * nunits - 1) return;  // the forward counting phase took the first nunits arrivals
+    // the forward counting phase took the first nunits arrivals (none at level 0)
+    if (prev != (lb > 0 ? 2 : 1) * nunits - 1) return;
     part_loads_after();
     acc = 0.0;
     for (int32_t cc = 0; cc < nunits; ++cc) acc += part_load(&a.part_m[(size_t)(un.pb + cc) * 64 + lane]);
   }
-  if (!om) return;
+  if (!om2) return;
   const double omw = a.omega ? (double)a.omega[w] : 0.0;
   double cs = 0.0;
-  if ((om >> lane) & 1ull) {
+  if ((om2 >> lane) & 1ull) {
     const double delta = sw * acc;
     psi[idx] = (1.0 + delta + omw) / sw;
     cs = lw * (delta + omw);
     if (a.delta_out) a.delta_out[(size_t)(64 * k + lane) * a.n + w] = delta;
   }
   // per (word, slot) sums in lane order
-  uint64_t rem = om;
+  uint64_t rem = om2;
   while (rem) {
     const int pv = __builtin_amdgcn_readlane(pr, __builtin_ctzll(rem));
     const uint64_t same = ballot(pr == pv) & rem;
@@ -717,7 +783,22 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
   {
     bool claimed = false;
     uint64_t ent = 0;
-    if (tid < (int64_t)B) {
+    if (tid < (int64_t)B && a.lane_pa[tid] >= 0) {
+      // a derived lane c (Lemma 1): its partners a and b sit at distance 1
+      // from c, each reached first by its own partner lane at level 0
+      const int j = (int)tid, w0 = j & ~63;
+      const uint64_t bit = 1ull << (j & 63);
+      const int32_t va = a.lane_src[w0 + a.lane_pa[j]], vb = a.lane_src[w0 + a.lane_pb[j]];
+      if (EXT) {
+        a.sm[(size_t)va * B + j] = 1.0; a.se[(size_t)va * B + j] = 0;
+        a.sm[(size_t)vb * B + j] = 1.0; a.se[(size_t)vb * B + j] = 0;
+      } else {
+        a.sig[(size_t)va * B + j] = 1ull;
+        a.sig[(size_t)vb * B + j] = 1ull;
+      }
+      atomicOr((unsigned long long*)&a.dla[(size_t)va * K + (j >> 6)], (unsigned long long)bit);
+      atomicOr((unsigned long long*)&a.dlb[(size_t)vb * K + (j >> 6)], (unsigned long long)bit);
+    } else if (tid < (int64_t)B) {
       const int32_t s = a.lane_src[tid];
       if (s >= 0) {
         const int j = (int)tid;
@@ -781,7 +862,8 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
         if (i < nu) {
           const BUnit un = a.U[ubase + i];
           const uint64_t nbm = cur[(size_t)un.v * K + un.k];
-          if (un.deg <= kLaneMaxDeg && __popcll(nbm) == 1 && (nbm & a.edge_lanes[un.k]) != 0)
+          if (un.deg <= kLaneMaxDeg && __popcll(nbm) == 1 && (nbm & a.edge_lanes[un.k]) != 0 &&
+              a.derived_lanes[un.k] == 0)
             lane_forward_unit<EXT>(a, st, un, nbm, par, cur, nxt, kl, kl >= 1, !bu, ebn, ubn, C);
           else
             dense = true;
@@ -829,28 +911,6 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
           C.newl += (uint64_t)__popcll(nb & ~old);
         }
         stage_append(a, st, nl, ebn, ubn, claimed, bentry(w, k));
-      }
-    }
-    if (a.has_derived) {
-      // 2-degree derived lanes: elementwise over the level-kl entries (Lemma 1)
-      for (int64_t i = gw; i < ne; i += nw) {
-        const uint64_t ent = a.Q[ebase + i];
-        const int32_t v = (int32_t)(uint32_t)ent;
-        const int k = (int)(ent >> 32);
-        const size_t vk = (size_t)v * K + k;
-        const uint64_t ck = cur[vk];
-        const uint64_t reached = a.vis[vk] | ck;
-        const int pa = a.lane_pa[64 * k + lane], pb = a.lane_pb[64 * k + lane];
-        bool mine = false;
-        if (pa >= 0) mine = ((((ck >> pa) | (ck >> pb)) & 1ull) != 0) && (((reached >> lane) & 1ull) == 0);
-        const uint64_t nb = ballot(mine);
-        bool claimed = false;
-        if (nb && lane == 0) {
-          const uint64_t old = atomicOr((unsigned long long*)&nxt[vk], (unsigned long long)nb);
-          claimed = old == 0ull;
-          C.newl += (uint64_t)__popcll(nb & ~old);
-        }
-        stage_append(a, st, nl, ebn, ubn, claimed, bentry(v, k));
       }
     }
     // level kl-2 masks are no longer read: clear them for reuse as level kl+2
@@ -945,7 +1005,10 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     // trace: keep the counts before psi overwrites them
     for (int64_t i = tid; i < (int64_t)n * (int64_t)B; i += nth) {
       const int32_t v = (int32_t)(i / (int64_t)B), j = (int32_t)(i % (int64_t)B);
-      const bool r = (a.vis[(size_t)v * K + (j >> 6)] >> (j & 63)) & 1ull;
+      const size_t vk = (size_t)v * K + (j >> 6);
+      bool r = (a.vis[vk] >> (j & 63)) & 1ull;
+      if (a.has_derived && ((a.derived_lanes[j >> 6] >> (j & 63)) & 1ull))  // reached through a partner
+        r = ((a.dla[vk] | a.dlb[vk]) >> (j & 63)) & 1ull;
       if (EXT) { a.sm_out[(size_t)j * n + v] = r ? a.sm[i] : 0.0; a.se_out[(size_t)j * n + v] = r ? a.se[i] : 0; }
       else a.sig_out[(size_t)j * n + v] = r ? a.sig[i] : 0ull;
     }
@@ -954,14 +1017,21 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
 
   // ---- backward sweep
   if (!failed) {
-    for (int lb = depth; lb >= 1; --lb) {
+    // level 0 only for derived lanes: their dependency at the partners'
+    // vertices (d_c = 1) is accumulated at the partners' sources
+    for (int lb = depth; lb >= (a.has_derived ? 0 : 1); --lb) {
       const uint64_t* cmv = F(lb + 1);
       uint64_t* own = F(lb);
       uint64_t* clr = F(lb + 2);
       const int32_t ub = a.uoff[lb], ue = a.uoff[lb + 1];
       const int64_t nub = ue - ub;
       if (threadIdx.x == 0) st.bclaim[(lb - 1) & 1] = 0;  // the next level's counter
-      if (ldr64(&a.lc[lb].lanes) < 2ull * (uint64_t)(a.qoff[lb + 1] - a.qoff[lb])) {
+      if (lb == 0) {
+        for (int64_t i = wg_claim(&st.bclaim[0]); i < nub; i = wg_claim(&st.bclaim[0])) {
+          const BUnit un = a.U[ub + i];
+          if (a.derived_lanes[un.k] != 0) backward_unit<EXT>(a, un, cmv, own, 0, depth, st);
+        }
+      } else if (ldr64(&a.lc[lb].lanes) < 2ull * (uint64_t)(a.qoff[lb + 1] - a.qoff[lb])) {
         // sparse level: one unit per lane where the word has at most one lane here
         for (int64_t first = gw; first < nub; first += nw * kWave) {
           const int64_t i = first + nw * lane;
@@ -969,7 +1039,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
           if (i < nub) {
             const BUnit un = a.U[ub + i];
             const uint64_t om = a.emask[un.e] & ~st.sX[un.k];
-            if (un.deg <= kLaneMaxDeg && __popcll(om) <= 1)
+            if (un.deg <= kLaneMaxDeg && __popcll(om) <= 1 && a.derived_lanes[un.k] == 0)
               lane_backward_unit<EXT>(a, un, om, cmv, own, lb, depth);
             else
               dense = true;
@@ -1011,8 +1081,10 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
       } else if (a.has_own && a.lane_own[j] != 0) {
         // each folded source reaches its component through s, except s and
         // its own subtree (Eq. (4) for pendants: own * (n_s - 2))
+        // (a derived lane's component is its partners')
+        const int jn = a.lane_pa[j] >= 0 ? (j & ~63) + a.lane_pa[j] : j;
         a.pair_bc[(size_t)a.lane_pair[j] * n + s] +=
-            (double)a.lane_own[j] * ((double)a.lane_ns[j] - 1.0) - a.lane_tsub[j];
+            (double)a.lane_own[j] * ((double)a.lane_ns[jn] - 1.0) - a.lane_tsub[j];
       }
     }
     atomicAdd(&a.stats[kStLevels], (unsigned long long)levels);
@@ -1042,6 +1114,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
       a.vis[i] = 0;
 #pragma unroll
       for (int s = 0; s < kSlots; ++s) a.fm[(size_t)s * fms + i] = 0;
+      if (a.has_derived) { a.dla[i] = 0; a.dlb[i] = 0; }
     }
   }
 }

@@ -289,25 +289,41 @@ void map_sources(int32_t n, const int32_t* rp, const Pruned* pr, const int32_t* 
 void choose_deg2(int32_t n, const int32_t* rp, const int32_t* ci, std::vector<Group>& groups,
                  std::vector<Triple>* triples) {
   triples->clear();
-  // triples only within one result slot (groups of one query)
+  // Derived vertices: c of degree 2 whose two neighbours are requested
+  // sources of the same result slot that are traversed (never derived
+  // themselves).  A neighbour may serve several derived vertices; every
+  // cluster (derived vertices and their partners, joined through shared
+  // partners) must fit one 64-lane word.  Greedy in source order.
   int nslot = 1;
   for (const auto& gr : groups) nslot = std::max(nslot, gr.slot + 1);
-  std::vector<int32_t> gi((size_t)n, -1);
-  std::vector<char> used(groups.size(), 0);
+  const size_t G = groups.size();
+  std::vector<int32_t> gi((size_t)n, -1), uf(G), size(G, 1);
+  std::vector<char> role(G, 0);  // 1 partner, 2 derived
+  for (size_t i = 0; i < G; ++i) uf[i] = (int32_t)i;
+  auto find = [&](int32_t x) {
+    while (uf[x] != x) x = uf[x] = uf[uf[x]];
+    return x;
+  };
   for (int sl = 0; sl < nslot; ++sl) {
-    for (size_t i = 0; i < groups.size(); ++i)
+    for (size_t i = 0; i < G; ++i)
       if (groups[i].slot == sl) gi[groups[i].v] = (int32_t)i;
-    for (size_t i = 0; i < groups.size(); ++i) {
-      if (groups[i].slot != sl) continue;
+    for (size_t i = 0; i < G; ++i) {
+      if (groups[i].slot != sl || role[i] != 0) continue;
       const int32_t c = groups[i].v;
-      if (used[i] || rp[c + 1] - rp[c] != 2) continue;
-      const int32_t a = ci[rp[c]], b = ci[rp[c] + 1];
-      const int32_t ia = gi[a], ib = gi[b];
-      if (ia < 0 || ib < 0 || used[ia] || used[ib]) continue;
-      used[i] = used[ia] = used[ib] = 1;
+      if (rp[c + 1] - rp[c] != 2) continue;
+      const int32_t ia = gi[ci[rp[c]]], ib = gi[ci[rp[c] + 1]];
+      if (ia < 0 || ib < 0 || role[ia] == 2 || role[ib] == 2) continue;
+      const int32_t ra = find(ia), rb = find(ib);
+      const int32_t merged = (ra == rb ? size[ra] : size[ra] + size[rb]) + 1;
+      if (merged > 64) continue;
+      role[i] = 2;
+      role[ia] = role[ib] = 1;
+      uf[ra] = (int32_t)i;
+      if (rb != ra) uf[rb] = (int32_t)i;
+      size[i] = merged;
       triples->push_back(Triple{ia, ib, (int32_t)i});
     }
-    for (size_t i = 0; i < groups.size(); ++i)
+    for (size_t i = 0; i < G; ++i)
       if (groups[i].slot == sl) gi[groups[i].v] = -1;
   }
 }

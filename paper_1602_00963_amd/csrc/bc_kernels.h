@@ -123,6 +123,9 @@ struct BatchArgs {
   int32_t npairs, cap_pairs;
   double* pair_bc;            // [cap_pairs][n] per-pair sums of one launch, zero between launches
   const uint64_t* edge_lanes; // [K] lanes that propagate along edges (active, not derived)
+  const uint64_t* derived_lanes; // [K] lanes derived from two partner lanes of their word
+  uint64_t* dla;              // [n][K] derived lanes c with d_a(v) <= d_b(v) at v (a, b: c's partners)
+  uint64_t* dlb;              // [n][K] derived lanes c with d_b(v) <= d_a(v)
   int32_t has_derived;        // any lane derived from two partner lanes
   int32_t has_own;            // any lane with pendant sources (component sizes needed)
   unsigned long long* fulledges; // edges x words whose word's edge lanes have all reached the vertex

@@ -368,6 +368,75 @@ def test_roadlike_grid_full_size_sampled(bcm, ctx):
     assert_close(got, ref, what="grid2048")
 
 
+def test_rmat_scale20_pendants_multi_launch(bcm, ctx):
+    """The scale-20 graph with pendants, pruned, in the benchmark's tuned
+    launch shape (128 sources per launch, top-down only) over several
+    launches: 600 sampled sources (pendants among them) against the
+    unpruned oracle."""
+    g = gg.workload_rmat20_pendants()
+    S = gg.sample(np.arange(g.n, dtype=np.int32), 600, 31)
+    say("case rmat20 pendants multi-launch", g.n, g.m)
+    ref, _ = oracle.bc(g, S, nthreads=16)
+    got, st = run_bc(bcm, ctx, g, S, prune=True, deg1=True, mode="batched", batch=128, alpha=-1.0)
+    assert st["launches"] >= 4, st["launches"]
+    assert_close(got, ref, what="rmat20 pendants multi-launch")
+
+
+def test_roadlike_grid_multi_launch_extended(bcm, ctx):
+    """The 2048 x 2048 lattice in automatic count form over several launches:
+    after the one-word probe nearly every source wraps, so the rest run in
+    extended form with worst-case lists (four launches of up to 256
+    sources); scores against the oracle's long-double reruns."""
+    g = gg.workload_roadlike_grid()
+    S = gg.sample(g.non_isolated(), 64 + 3 * 256 + 10, 29)
+    say("case grid2048 multi-launch", g.n, g.m)
+    ref, ovf = oracle.bc(g, S, nthreads=16)
+    got, st = run_bc(bcm, ctx, g, S, mode="batched", batch=256)
+    assert ovf.mean() > 0.5 and st["launches"] >= 5, (ovf.mean(), st["launches"])
+    assert_close(got, ref, what="grid2048 multi-launch")
+
+
+def test_degree2_derivation_extended_counts(bcm, ctx):
+    """2-degree derivation on a long-diameter lattice whose counts wrap
+    uint64: after the one-word probe the batches run in extended form with
+    derived lanes (Eq. (6) on significand/exponent pairs); scores against
+    the oracle's long-double reruns."""
+    g = gg.road_grid(72, 72, 0.2, 0.0, 5)
+    say("case deg2 extended", g.n, g.m)
+    G = bcm.Graph(ctx, g)
+    st = G.compute(None, mode="batched", batch=256, deg2=True)
+    got = G.scores()
+    G.close()
+    ref, ovf = oracle.bc(g, nthreads=16)
+    assert ovf.mean() > 0.5 and st["derived"] > 200, (ovf.mean(), st["derived"])
+    assert_close(got, ref, what="deg2 extended")
+
+
+@pytest.mark.parametrize("batch", [64, 256])
+def test_degree2_derived_lanes_traced(bcm, ctx, batch):
+    """2-degree vertices derived from their partner lanes (Lemma 1, Eq. (6))
+    with the fused backward sweep: their counts and dependencies, as the
+    kernel computes them, equal a BFS/Brandes sweep from the vertex itself
+    (counts bit-exact, levels from the partners' levels bit-exact,
+    dependencies within 1e-9)."""
+    g = gg.disjoint_union(gg.road_grid(24, 20, 0.2, 0.01, 7), gg.cycle(9), gg.path(7))
+    S = np.arange(g.n, dtype=np.int32)
+    say("case deg2 traced", batch)
+    G = bcm.Graph(ctx, g)
+    st = G.compute(S, mode="batched", batch=batch, deg2=True)
+    assert st["derived"] > 20
+    tr = G.trace(S, mode="batched", batch=batch, deg2=True)
+    G.close()
+    for i, s in enumerate(S):
+        o = oracle.source(g, int(s))
+        assert np.array_equal(tr["d"][i], o["d"]), f"d differs for source {s}"
+        if not o["overflow"]:
+            assert np.array_equal(tr["sigma"][i], o["sigma"]), f"sigma differs for source {s}"
+        dl = o["delta"].copy()
+        dl[s] = 0.0
+        assert_close(tr["delta"][i], dl, what=f"delta of source {s}")
+
+
 def test_rmat_scale16_hub_sources_traced(bcm, ctx):
     """Per-source d and sigma bit-exact at full size for sources next to the
     highest-degree vertices: their adjacency lists span many work units, so

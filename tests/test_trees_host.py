@@ -74,3 +74,27 @@ def test_one_round_is_not_iterated():
     one = bcm.prune_deg1_host(g.n, g.row_ptr, g.col_idx)
     it = bcm.prune_trees_host(g.n, g.row_ptr, g.col_idx)
     assert one["omega"].sum() <= it["omega"].sum() and it["omega"].sum() == 4
+
+
+def test_coverage_counts():
+    """Heuristics coverage (host): every non-isolated source is traversed,
+    served by the 1-degree reduction or derived by the 2-degree heuristic;
+    on a cycle the derived vertices are a maximum independent set (floor(n/2))
+    with every derived vertex's neighbours traversed."""
+    for n in (9, 10, 11, 64):
+        g = gg.cycle(n)
+        c = bcm.coverage_host(g.n, g.row_ptr, g.col_idx, deg2=True)
+        assert c["two_degree"] == n // 2 and c["traversed"] == n - n // 2
+    g = gg.disjoint_union(gg.road_grid(40, 40, 0.1, 0.01, 3), gg.star(5), gg.path(1),
+                          gg.attach_trees(gg.cycle(12), [3, 4], 2))
+    base = bcm.coverage_host(g.n, g.row_ptr, g.col_idx)
+    assert base["traversed"] == base["sources"] == g.n - 1  # one isolated vertex
+    for prune in (True, "trees"):
+        for deg2 in (False, True):
+            c = bcm.coverage_host(g.n, g.row_ptr, g.col_idx, prune=prune, deg1=True, deg2=deg2)
+            assert c["sources"] == c["traversed"] + c["one_degree"] + c["two_degree"]
+            assert c["one_degree"] > 0 and (c["two_degree"] > 0) == deg2
+            assert c["two_degree"] <= c["deg2_candidates"]
+    it = bcm.coverage_host(g.n, g.row_ptr, g.col_idx, prune="trees", deg1=True)
+    one = bcm.coverage_host(g.n, g.row_ptr, g.col_idx, prune=True, deg1=True)
+    assert it["one_degree"] > one["one_degree"]
