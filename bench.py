@@ -40,8 +40,11 @@ def workload(name: str, sources_arg: int):
         g, wl, prune = gg.workload_rmat20_pendants(), "rmat20_ef16_plus30pct_pendants_pruned", True
     elif name == "grid2048":
         g, wl, prune = gg.workload_roadlike_grid(), "grid2048_roadlike_all_sources", False
+    elif name == "strip":
+        # a 16384 x 4 lattice strip: a long diameter (16,386 levels) with counts that fit 64 bits
+        g, wl, prune = gg.full_grid(16384, 4), "strip16384x4_lattice_all_sources", False
     else:
-        raise SystemExit(f"unknown workload {name} (rmat10, rmat16, rmat20p, grid2048)")
+        raise SystemExit(f"unknown workload {name} (rmat10, rmat16, rmat20p, grid2048, strip)")
     if sources_arg < 0:
         sources_arg = DEFAULT_SOURCES.get(name, 0)
     src = None
@@ -394,6 +397,7 @@ def main():
     ap.add_argument("--alpha", type=float, default=None,
                     help="bottom-up threshold (0 = library default, < 0 = never; "
                          "unset = the workload's measured best: -1 on the R-MAT graphs)")
+    ap.add_argument("--beta", type=float, default=0.0, help="bottom-up switch-back threshold (0 = none)")
     ap.add_argument("--grid-per-cu", type=int, default=0)
     ap.add_argument("--deg2", action="store_true")
     ap.add_argument("--autotune", type=int, default=-1,
@@ -474,7 +478,7 @@ def main():
     G = bcm.Graph(ctx, g, validate=False, prune=prune)
     stream = torch.cuda.Stream()
     opts = dict(mode=args.mode, batch=args.batch, deg1=prune, deg2=args.deg2, alpha=args.alpha,
-                grid_per_cu=args.grid_per_cu)
+                grid_per_cu=args.grid_per_cu, beta=args.beta)
     tuned = None
     if args.autotune > 0 and args.mode == "batched":
         import graphgen as gg
@@ -484,7 +488,7 @@ def main():
                            deg2=args.deg2)
         tuned["seconds"] = round(time.perf_counter() - t0, 2)
         log(f"autotune: {tuned}")
-        opts.update(batch=0, alpha=0.0, grid_per_cu=0)
+        opts.update(batch=0, alpha=0.0, grid_per_cu=0, beta=0.0)
     for i in range(args.warmup):
         st, ms = timed_compute(G, sources, stream, **opts)
         log(f"warmup {i}: {ms:.1f} ms, launches {st['launches']}")
@@ -515,12 +519,14 @@ def main():
         "vs_baseline": None, "dtype": "u64+f64", "data": "synthetic",
         "config": {"workload": wl, "n": n, "m": m, "sources": int(st["sources"]), "traversed": int(st["traversed"]),
                    "mode": args.mode, "batch": tuned["batch"] if tuned else args.batch,
-                   "bottom_up_alpha": tuned["alpha"] if tuned else args.alpha, "pruned": prune,
+                   "bottom_up_alpha": tuned["alpha"] if tuned else args.alpha,
+                   "bottom_up_beta": tuned["beta"] if tuned else args.beta, "pruned": prune,
                    "deg2": args.deg2, "autotuned": tuned},
         "gteps_2m": round(2 * gteps, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel_sha": kernel_sha(),
-                     "kernel": "batch_kernel" if args.mode == "batched" else "plain_kernel",
+                     "kernel": {"batched": "batch_kernel", "plain": "plain_kernel",
+                                "plain_scan": "scan_kernel"}[args.mode],
                      "avg_launch_ms": round(per_launch_ms, 4), "launches": int(st["launches"]),
                      "kernel_ms_per_step": round(kern_ms, 2), "event_ms_per_step": round(float(np.median(times)), 2),
                      "launch_gap_us": round((float(np.median(times)) - kern_ms) * 1e3 / max(st["launches"], 1), 1),

@@ -108,7 +108,12 @@ bc_status bc_graph_free(bc_graph* g);
 
 enum {
   BC_MODE_PLAIN = 0,    /* one cooperative launch per source */
-  BC_MODE_BATCHED = 1   /* one cooperative launch per batch of `batch` sources */
+  BC_MODE_BATCHED = 1,  /* one cooperative launch per batch of `batch` sources */
+  BC_MODE_PLAIN_SCAN = 2 /* one source per launch with the paper's active-edge mapping (Sec. 3.1):
+                            per level a prefix sum of the frontier's degrees and a binary search
+                            per edge, the prefix sums reused by the backward sweep; exact counts
+                            (wrapped sources are rerun by BC_MODE_PLAIN in extended form), no
+                            direction switching, no heuristics; for comparison with BC_MODE_PLAIN */
 };
 enum {
   BC_H_DEG1 = 1u,       /* use the graph's 1-degree reduction (needs BC_LOAD_PRUNE_DEG1) */
@@ -129,6 +134,9 @@ typedef struct bc_compute_opts {
                            (tuned if available, else 1 batched / 4 plain), < 0 = never bottom-up */
   int32_t block;        /* threads per workgroup: 0, or the mode's fixed size (1024 batched, 256 plain) */
   int32_t grid_per_cu;  /* workgroups per CU for the persistent grid; 0 = occupancy limit */
+  double beta;          /* switch back: a bottom-up sweep stays bottom-up until the frontier holds
+                           fewer than n / beta vertices (batched: (vertex, word) entries against
+                           n * words); 0 = no hysteresis (tuned if available), each level tests alpha */
 } bc_compute_opts;
 
 typedef struct bc_run_stats {
@@ -190,7 +198,8 @@ bc_status bc_compute_noalloc(bc_graph* g, const int32_t* sources, int64_t k, con
  * Autotuner for the batched mode: times trial runs of `sample` (k source
  * ids, at least two batches' worth recommended) into a scratch score array
  * (the graph's scores are untouched) over batch width {64, 128, 256, 512, 1024},
- * the bottom-up threshold alpha {0 = never, 0.5, 1, 2, 4, 8} and the
+ * the bottom-up threshold alpha {0 = never, 0.5, 1, 2, 4, 8}, its switch-back
+ * threshold beta {0, 2, 8, 24, 64} (when bottom-up is in play) and the
  * persistent grid {occupancy limit, half of it}, by coordinate descent
  * starting from *opts.  On return *opts holds the fastest setting found
  * (mode, heuristics and sigma_mode are kept) and *gteps its throughput

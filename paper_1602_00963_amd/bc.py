@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libbc.so")
 OK, E_INVALID_ARG, E_INVALID_GRAPH, E_OUT_OF_MEMORY, E_DEVICE, E_BUSY, E_NOT_FOUND, E_TIMEOUT, E_REJECTED, \
     E_CAPACITY = range(10)
 LOAD_VALIDATE, LOAD_PRUNE_DEG1, LOAD_DEVICE_PTRS, LOAD_KEEP_ORDER, LOAD_PRUNE_TREES = 1, 2, 4, 8, 16
-MODE_PLAIN, MODE_BATCHED = 0, 1
+MODE_PLAIN, MODE_BATCHED, MODE_PLAIN_SCAN = 0, 1, 2
 H_DEG1, H_DEG2 = 1, 2
 SIGMA_AUTO, SIGMA_EXACT_ONLY, SIGMA_EXTENDED = 0, 1, 2
 RAW, UNDIRECTED = 0, 1
@@ -41,7 +41,7 @@ class GraphStats(ctypes.Structure):
 class ComputeOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("batch", ctypes.c_int32), ("heuristics", ctypes.c_uint32),
                 ("sigma_mode", ctypes.c_int32), ("alpha", ctypes.c_double), ("block", ctypes.c_int32),
-                ("grid_per_cu", ctypes.c_int32)]
+                ("grid_per_cu", ctypes.c_int32), ("beta", ctypes.c_double)]
 
 
 class RunStats(ctypes.Structure):
@@ -210,15 +210,16 @@ class Context:
             pass
 
 
-def make_opts(mode="batched", batch=256, deg1=False, deg2=False, sigma="auto", alpha=0.0, grid_per_cu=0):
+def make_opts(mode="batched", batch=256, deg1=False, deg2=False, sigma="auto", alpha=0.0, grid_per_cu=0, beta=0.0):
     o = ComputeOpts()
-    o.mode = {"plain": MODE_PLAIN, "batched": MODE_BATCHED}[mode]
+    o.mode = {"plain": MODE_PLAIN, "batched": MODE_BATCHED, "plain_scan": MODE_PLAIN_SCAN}[mode]
     o.batch = batch
     o.heuristics = (H_DEG1 if deg1 else 0) | (H_DEG2 if deg2 else 0)
     o.sigma_mode = {"auto": SIGMA_AUTO, "exact": SIGMA_EXACT_ONLY, "extended": SIGMA_EXTENDED}[sigma]
     o.alpha = alpha
     o.block = 0
     o.grid_per_cu = grid_per_cu
+    o.beta = beta
     return o
 
 
@@ -298,7 +299,7 @@ class Graph:
         gt = ctypes.c_double(0.0)
         _check(lib().bc_autotune(self.h, _p(src), len(src), ctypes.byref(o), budget_ms, ctypes.byref(gt)),
                "bc_autotune")
-        return {"batch": o.batch, "alpha": o.alpha, "grid_per_cu": o.grid_per_cu, "gteps": gt.value}
+        return {"batch": o.batch, "alpha": o.alpha, "beta": o.beta, "grid_per_cu": o.grid_per_cu, "gteps": gt.value}
 
     def scores(self, norm: str = "raw", out=None) -> np.ndarray:
         """Accumulated scores; `out` may be a torch float64 device tensor."""

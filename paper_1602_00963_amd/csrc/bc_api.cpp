@@ -100,6 +100,48 @@ size_t plain_layout(int64_t n, int64_t nnz, char* base, PlainWs* w) {
   return c.off;
 }
 
+struct ScanWs {
+  int32_t *d, *Q, *qoff, *err, *ovf_now, *ovf_list, *ovf_count;
+  uint64_t* sig;
+  double *psi, *acc, *delta, *bc_tmp;
+  int64_t *cd, *tot, *bsum;
+  unsigned long long* stats;
+  GridBar* bar;
+  size_t ctl_bytes;
+  char* ctl_begin;
+};
+
+constexpr int kScanMaxGrid = 4096;
+
+size_t scan_layout(int64_t n, char* base, ScanWs* w) {
+  Carve c{base};
+  ScanWs t{};
+  t.d = c.take<int32_t>(n);
+  t.sig = c.take<uint64_t>(n);
+  t.psi = c.take<double>(n);
+  t.acc = c.take<double>(n);
+  t.Q = c.take<int32_t>(n);
+  t.qoff = c.take<int32_t>(n + 3);
+  t.cd = c.take<int64_t>(n);
+  t.tot = c.take<int64_t>(n + 1);
+  t.bsum = c.take<int64_t>(kScanMaxGrid);
+  t.ovf_list = c.take<int32_t>(n + 1);
+  t.delta = c.take<double>(n);
+  t.bc_tmp = c.take<double>(n);
+  c.off = align_up(c.off, 256);
+  const size_t ctl0 = c.off;
+  t.err = c.take<int32_t>(1);
+  t.ovf_now = c.take<int32_t>(1);
+  t.ovf_count = c.take<int32_t>(1);
+  t.stats = c.take<unsigned long long>(kStCount);
+  t.bar = c.take<GridBar>(1);
+  c.off = align_up(c.off, 256);
+  t.ctl_bytes = c.off - ctl0;
+  t.ctl_begin = base ? base + ctl0 : nullptr;
+  if (w) *w = t;
+  return c.off;
+}
+
 struct BatchCaps {
   int64_t entries, units, parts, multi;
 };
@@ -235,7 +277,7 @@ struct bc_graph {
   // batched-mode setting chosen by bc_autotune
   bool tuned = false;
   int32_t tuned_batch = 0, tuned_grid = 0;
-  double tuned_alpha = 0.0;
+  double tuned_alpha = 0.0, tuned_beta = 0.0;
   // batching order of sources (computed on the first batched call)
   std::vector<int32_t> rank;
   std::once_flag rank_once;
@@ -577,7 +619,8 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
   bc_compute_opts d{};
   if (!o) o = &d;
   r->mode = o->mode;
-  if (r->mode != BC_MODE_PLAIN && r->mode != BC_MODE_BATCHED) return fail(BC_E_INVALID_ARG, "unknown mode");
+  if (r->mode != BC_MODE_PLAIN && r->mode != BC_MODE_BATCHED && r->mode != BC_MODE_PLAIN_SCAN)
+    return fail(BC_E_INVALID_ARG, "unknown mode");
   r->B = o->batch ? o->batch : (g->tuned ? g->tuned_batch : 256);
   if (r->B % 64 != 0 || r->B < 64 || r->B > 64 * kMaxWords)
     return fail(BC_E_INVALID_ARG, "batch must be a multiple of 64 from 64 to 1024");
@@ -592,16 +635,22 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
   r->deg2 = (o->heuristics & BC_H_DEG2) != 0;
   if (r->deg1 && !g->pruned) return fail(BC_E_INVALID_ARG, "BC_H_DEG1 needs a graph loaded with BC_LOAD_PRUNE_DEG1");
   if (r->deg2 && r->mode != BC_MODE_BATCHED) return fail(BC_E_INVALID_ARG, "BC_H_DEG2 needs the batched mode");
+  if (r->mode == BC_MODE_PLAIN_SCAN && (r->deg1 || r->sigma_mode == BC_SIGMA_EXTENDED))
+    return fail(BC_E_INVALID_ARG, "BC_MODE_PLAIN_SCAN takes no heuristics and exact counts");
   if (o->alpha > 0) r->alpha = o->alpha;
   else if (o->alpha < 0) r->alpha = 0.0;  // never bottom-up
   else if (g->tuned && !o->batch && r->mode == BC_MODE_BATCHED) r->alpha = g->tuned_alpha;
   else r->alpha = r->mode == BC_MODE_PLAIN ? 4.0 : 1.0;
+  if (o->beta < 0) return fail(BC_E_INVALID_ARG, "beta must be >= 0");
+  r->beta = o->beta > 0 ? o->beta : (g->tuned && !o->batch && r->mode == BC_MODE_BATCHED ? g->tuned_beta : 0.0);
   return BC_OK;
 }
 
 size_t ws_bytes_for(const bc_graph* g, const Resolved& r, int cap_factor) {
   cap_factor = std::max(cap_factor, r.cap_factor);
   if (r.mode == BC_MODE_PLAIN) return plain_layout(g->n, g->nnz, nullptr, nullptr);
+  if (r.mode == BC_MODE_PLAIN_SCAN)  // wrapped sources rerun in the plain workspace
+    return std::max(scan_layout(g->n, nullptr, nullptr), plain_layout(g->n, g->nnz, nullptr, nullptr));
   return batch_layout(g->n, g->nnz, r.B, cap_factor, r.max_slots, r.trace, nullptr, nullptr);
 }
 
@@ -927,6 +976,7 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   a.clear_at_end = tr ? 0 : 1;
   a.keep_lv = (tr && w.lv) ? 1 : 0;
   a.alpha = r.alpha;
+  a.beta = r.beta;
   a.cap_entries = (int32_t)w.caps.entries;
   a.cap_units = (int32_t)w.caps.units;
   a.cap_parts = (int32_t)w.caps.parts;
@@ -1021,6 +1071,7 @@ bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& t
   a.bc = bc;
   a.delta_out = delta_out;
   a.alpha = r.alpha;
+  a.beta = r.beta;
   a.cap_entries = g->n;
   a.cap_units = (int32_t)plain_cap_units(g->n, g->nnz);
   a.cap_parts = (int32_t)plain_cap_parts(g->n, g->nnz);
@@ -1048,6 +1099,62 @@ bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& t
   if (ex) HIPCHK(ex->collect(&out->kernel_ms));
   if (err & kErrBarrier) return fail(BC_E_DEVICE, "grid-barrier wait gave up: the persistent grid was not resident");
   out->err = err;
+  out->ovf.resize(std::min<int32_t>(cnt, g->n + 1));
+  if (cnt) HIPCHK(hipMemcpy(out->ovf.data(), w.ovf_list, sizeof(int32_t) * out->ovf.size(), hipMemcpyDeviceToHost));
+  return BC_OK;
+}
+
+// One source per launch with the paper's prefix-sum / binary-search mapping.
+bc_status run_scan(bc_graph* g, const Resolved& r, const TravGraph& tg, const std::vector<Group>& groups,
+                   char* wsbase, hipStream_t st, double* bc, Exec* ex, CallOut* out) {
+  if (ex) ex->used = 0;
+  ScanWs w;
+  scan_layout(g->n, wsbase, &w);
+  HIPCHK(hipMemsetAsync(w.ctl_begin, 0, w.ctl_bytes, st));
+  int bpc = 1;
+  if (scan_max_grid(&bpc) != hipSuccess || bpc < 1) bpc = 1;
+  const int grid = std::min(kScanMaxGrid, g->ctx->cus * std::min(bpc, 2));
+  ScanArgs a{};
+  a.n = g->n;
+  a.rp = tg.rp;
+  a.ci = tg.ci;
+  a.d = w.d;
+  a.sig = w.sig;
+  a.psi = w.psi;
+  a.acc = w.acc;
+  a.Q = w.Q;
+  a.qoff = w.qoff;
+  a.cd = w.cd;
+  a.tot = w.tot;
+  a.bsum = w.bsum;
+  a.err = w.err;
+  a.ovf_now = w.ovf_now;
+  a.ovf_list = w.ovf_list;
+  a.ovf_count = w.ovf_count;
+  a.stats = w.stats;
+  a.bar = w.bar;
+  a.bar_limit = g->ctx->bar_ticks;
+  a.bc = bc;
+  a.delta_out = nullptr;
+  for (const auto& gr : groups) {
+    a.src = gr.v;
+    a.weight = gr.w;
+    if (ex) HIPCHK(ex->mark(st));
+    HIPCHK(launch_scan(a, grid, st));
+    if (!ex) continue;
+    HIPCHK(ex->mark(st));
+    if (ex->used >= 512) {
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(ex->collect(&out->kernel_ms));
+    }
+  }
+  int32_t cnt = 0, err = 0;
+  HIPCHK(hipMemcpyAsync(&cnt, w.ovf_count, sizeof cnt, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&err, w.err, sizeof err, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(out->st, w.stats, sizeof(out->st), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (ex) HIPCHK(ex->collect(&out->kernel_ms));
+  if (err & kErrBarrier) return fail(BC_E_DEVICE, "grid-barrier wait gave up: the persistent grid was not resident");
   out->ovf.resize(std::min<int32_t>(cnt, g->n + 1));
   if (cnt) HIPCHK(hipMemcpy(out->ovf.data(), w.ovf_list, sizeof(int32_t) * out->ovf.size(), hipMemcpyDeviceToHost));
   return BC_OK;
@@ -1100,7 +1207,8 @@ static bc_status run_groups(bc_graph* g, const Resolved& r, bool ext, const Trav
   char* ws = nullptr;
   bc_status s = get_ws(g, ws_bytes_for(g, r, r.cap_factor), user_ws, user_bytes, &ws);
   if (s != BC_OK) return s;
-  if (r.mode == BC_MODE_PLAIN) {
+  if (r.mode == BC_MODE_PLAIN_SCAN && !ext) return run_scan(g, r, tg, groups, ws, st, slots[0], ex, out);
+  if (r.mode == BC_MODE_PLAIN || r.mode == BC_MODE_PLAIN_SCAN) {  // (wrapped scan sources: extended plain form)
     s = run_plain(g, r, ext, tg, groups, ws, st, slots[0], nullptr, ex, out);
     if (s == BC_OK && out->err) return fail(BC_E_CAPACITY, "level-list capacity exceeded");
     return s;
@@ -1380,6 +1488,8 @@ bc_status bc_autotune(bc_graph* g, const int32_t* sample, int64_t k, bc_compute_
   };
   for (int B : {64, 128, 256, 512, 1024}) { bc_compute_opts o = best; o.batch = B; if (B != best.batch) consider(o); }
   for (double al : {-1.0, 0.5, 1.0, 2.0, 4.0, 8.0}) { bc_compute_opts o = best; o.alpha = al; consider(o); }
+  if (best.alpha >= 0)  // bottom-up in play: its switch-back threshold
+    for (double be : {2.0, 8.0, 24.0, 64.0}) { bc_compute_opts o = best; o.beta = be; consider(o); }
   {
     int occ = 0;
     if (batch_max_grid(false, kBatchBlock, &occ) == hipSuccess && occ > 1) {
@@ -1396,6 +1506,7 @@ bc_status bc_autotune(bc_graph* g, const int32_t* sample, int64_t k, bc_compute_
   g->tuned_batch = best.batch;
   g->tuned_alpha = best.alpha > 0 ? best.alpha : (best.alpha < 0 ? 0.0 : 1.0);
   g->tuned_grid = best.grid_per_cu;
+  g->tuned_beta = best.beta;
   *opts = best;
   if (gteps) *gteps = (double)credited * (double)(g->nnz / 2) / (best_ms * 1e-3) / 1e9;
   return BC_OK;
@@ -1430,6 +1541,7 @@ static bc_status trace_internal(bc_graph* g, const int32_t* sources, int64_t k, 
   if (s != BC_OK) return s;
   if (r.deg1 || (r.deg2 && r.mode != BC_MODE_BATCHED))
     return fail(BC_E_INVALID_ARG, "traces run on the unpruned graph (2-degree derivation: batched only)");
+  if (r.mode == BC_MODE_PLAIN_SCAN) return fail(BC_E_INVALID_ARG, "traces run in the plain or batched mode");
   r.trace = true;
   for (int64_t i = 0; i < k; ++i)
     if (sources[i] < 0 || sources[i] >= g->n) return fail(BC_E_INVALID_ARG, "source id out of range");

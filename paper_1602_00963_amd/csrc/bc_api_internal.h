@@ -36,6 +36,7 @@ struct Resolved {
   int mode, B, K, block, grid_per_cu, sigma_mode;
   bool deg1, deg2;
   double alpha;
+  double beta = 0.0;    // bottom-up hysteresis (0 = none)
   int cap_factor = 32;  // batched level-list capacity: n * min(B, cap_factor) entries
   int max_slots = 1;    // result slots one batch may feed (the server packs up to 64)
   int grid_total = 0;   // cap on the persistent grid's workgroups (the server's share of the device); 0 = none

@@ -828,7 +828,7 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
   int32_t ebase = 0, ubase = 0;   // level kl's list
   int32_t eprev = 0, eprev2 = 0;  // starts of levels kl-1 and kl-2
   int levels = 0, bu_levels = 0;
-  bool failed = false;
+  bool failed = false, was_bu = false;
   while (true) {
     if (ldr32(&a.lc[kl].err) != 0) { failed = true; break; }
     const uint64_t pk = ldr64(&a.lc[kl].packed);
@@ -841,10 +841,14 @@ __global__ void __launch_bounds__(kBatchBlock) __attribute__((amdgpu_waves_per_e
     uint64_t* nxt = F(nl);
     uint64_t* clr = F(kl + 2);                 // level kl-2
     // direction: bottom-up once the frontier's edges outweigh alpha times
-    // the edges still undiscovered (both counted once per word)
+    // the edges still undiscovered (both counted once per word); with beta,
+    // a bottom-up sweep stays bottom-up until the frontier holds fewer than
+    // n / beta (vertex, word) entries
     const double fe = (double)ldr64(&a.lc[kl].fedges);
     const double unvisited = (double)a.nnz * kact - (double)ldr64(a.fulledges);
-    const bool bu = kl > 0 && a.alpha > 0.0 && fe * a.alpha > unvisited;
+    bool bu = kl > 0 && a.alpha > 0.0 && fe * a.alpha > unvisited;
+    if (was_bu && a.beta > 0.0) bu = (double)ne * a.beta >= (double)n * kact;
+    was_bu = bu;
     if (threadIdx.x == 0) st.fclaim[nl & 1] = 0;  // phase kl+1's counter; kl-1 used it before the barrier
     if (tid == 0) {
       a.qoff[nl] = ebn;

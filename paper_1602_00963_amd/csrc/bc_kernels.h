@@ -56,6 +56,7 @@ struct PlainArgs {
   double tsub;                // sum over them of the size of src's subtree that holds them
   double weight;              // sources represented by src's sweep
   double alpha;
+  double beta;                // stay bottom-up while frontier vertices * beta >= n (0: no hysteresis)
   int32_t cap_entries, cap_units, cap_parts, cap_multi, cap_levels;
 };
 
@@ -133,6 +134,7 @@ struct BatchArgs {
   uint64_t bar_limit;         // wall-clock ticks a grid-barrier wait may last
   int32_t clear_at_end;       // clear the masks before returning (off for traces)
   double alpha;
+  double beta;                // stay bottom-up while frontier entries * beta >= n * words (0: no hysteresis)
   int32_t cap_entries, cap_units, cap_parts, cap_levels;
 };
 
@@ -141,7 +143,37 @@ constexpr int kMaxWords = 16;    // batches of up to 1024 sources
 constexpr int kBatchBlock = 1024; // threads per workgroup of the batched kernel (one per CU)
 constexpr int kPlainChunkHost = 64;
 
+// One source per launch with the paper's active-edge mapping (prefix sum of
+// frontier degrees + binary search per edge, prefix sums reused backward).
+struct ScanArgs {
+  int32_t n;
+  const int32_t* rp;
+  const int32_t* ci;
+  int32_t* d;
+  uint64_t* sig;
+  double* psi;                // (1 + delta) / sigma of finished vertices
+  double* acc;                // backward accumulators
+  int32_t* Q;                 // frontiers, level after level
+  int32_t* qoff;              // [levels + 2] level starts; qoff[l + 2] counts level l+1's appends meanwhile
+  int64_t* cd;                // [n] exclusive prefix sum of degrees within each level (aligned with Q)
+  int64_t* tot;               // [levels] edges of each level's frontier
+  int64_t* bsum;              // [grid] chunk totals of the scan
+  int32_t* err;
+  int32_t* ovf_now;
+  int32_t* ovf_list;
+  int32_t* ovf_count;
+  unsigned long long* stats;
+  GridBar* bar;
+  uint64_t bar_limit;
+  double* bc;
+  double* delta_out;
+  int32_t src;
+  double weight;
+};
+
 hipError_t launch_plain(const PlainArgs& a, bool ext, int grid, int block, hipStream_t st);
+hipError_t launch_scan(const ScanArgs& a, int grid, hipStream_t st);
+hipError_t scan_max_grid(int* blocks_per_cu);
 hipError_t plain_max_grid(bool ext, int block, int* blocks_per_cu);
 
 hipError_t launch_batch(const BatchArgs& a, bool ext, int grid, int block, hipStream_t st);

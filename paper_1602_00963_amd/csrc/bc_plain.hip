@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
   int32_t ebase = 0, ubase = 0;
   int64_t visited_edges = 0;
   int levels = 0, bu_levels = 0;
-  bool failed = false;
+  bool failed = false, was_bu = false;
   while (true) {
     if (ld_relaxed(&a.lc[l].err) != 0) { failed = true; break; }
     const unsigned long long pk = __hip_atomic_load(&a.lc[l].packed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -114,7 +114,12 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
     const unsigned long long fe = __hip_atomic_load(&a.lc[l].fedges, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     visited_edges += (int64_t)fe;
     const int64_t unvisited = a.nnz - visited_edges;
-    const bool bu = l > 0 && a.alpha > 0.0 && (double)fe * a.alpha > (double)unvisited;
+    // direction: bottom-up once the frontier's edges outweigh alpha times
+    // the edges still unvisited; with beta, a bottom-up sweep stays
+    // bottom-up until the frontier holds fewer than n / beta vertices
+    bool bu = l > 0 && a.alpha > 0.0 && (double)fe * a.alpha > (double)unvisited;
+    if (was_bu && a.beta > 0.0) bu = (double)ne * a.beta >= (double)n;
+    was_bu = bu;
     const int32_t ebn = ebase + ne, ubn = ubase + nu;
     const int32_t nl = l + 1;
     if (tid == 0) {

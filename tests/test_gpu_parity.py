@@ -264,6 +264,49 @@ def test_bottom_up_levels_forced(bcm, ctx, opts):
     assert_close(got, ref, what=f"bottom-up lattice {opts}")
 
 
+@pytest.mark.parametrize("opts", [dict(mode="plain"), dict(mode="batched", batch=128)], ids=["plain", "b128"])
+def test_bottom_up_switch_back(bcm, ctx, opts):
+    """Direction switching with hysteresis: once bottom-up, a sweep stays
+    bottom-up until the frontier holds fewer than n / beta vertices; levels
+    and counts stay bit-exact and scores match the oracle whichever
+    direction each level takes."""
+    g = gg.rmat(11, 16, 41)
+    S = gg.sample(g.non_isolated(), 200, 42)
+    ref, _ = oracle.bc(g, S)
+    say("case switch-back", opts)
+    levels = {}
+    for beta in (0.0, 2.0, 1000.0):
+        got, st = run_bc(bcm, ctx, g, S, alpha=2.0, beta=beta, **opts)
+        assert_close(got, ref, what=f"beta {beta} {opts}")
+        levels[beta] = st["bottom_up_levels"]
+    # beta changes the schedule (longer bottom-up runs, earlier switch back
+    # on the small tail frontiers), never the results
+    assert len(set(levels.values())) > 1 and min(levels.values()) > 0, levels
+    tr = bcm.Graph(ctx, g).trace(S[:64], alpha=2.0, beta=1000.0, **opts)
+    for i, s in enumerate(S[:64]):
+        o = oracle.source(g, s)
+        assert np.array_equal(tr["d"][i], o["d"]) and np.array_equal(tr["sigma"][i], o["sigma"]), s
+
+
+def test_paper_mapping_mode(bcm, ctx):
+    """The paper's active-edge mapping (per level a prefix sum of the
+    frontier's degrees, a binary search per edge, the prefix sums reused by
+    the backward sweep) gives the oracle's scores: an R-MAT graph, a
+    long-diameter road-like strip, a union with isolated vertices and
+    repeated sources, and a lattice whose corner counts wrap (those sources
+    are rerun by the plain form in extended counts)."""
+    cases = [(gg.rmat(11, 16, 5), None),
+             (gg.road_grid(300, 4, 0.05, 0.01, 3), None),
+             (gg.disjoint_union(gg.rmat(9, 8, 2), gg.star(7), gg.path(1), gg.cycle(6)), np.array([0, 0, 3, 512, 513, 520, 521, 5], np.int32)),
+             (gg.full_grid(40, 40), np.array([0, 39, 1560, 1599, 820, 410], np.int32))]
+    for g, S in cases:
+        say("case plain_scan", g.name)
+        ref, ovf = oracle.bc(g, S)
+        got, st = run_bc(bcm, ctx, g, S, mode="plain_scan")
+        assert_close(got, ref, what=f"plain_scan {g.name}")
+        assert st["overflowed"] == int(ovf.sum())
+
+
 def test_sources_with_repeats_and_isolated(bcm, ctx):
     g = gg.disjoint_union(gg.rmat(9, 8, 2), gg.complete(1))
     nz = g.non_isolated()
