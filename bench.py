@@ -37,7 +37,7 @@ def workload(name: str, sources_arg: int):
     elif name == "rmat16":
         g, wl, prune = gg.workload_rmat16(), "rmat16_ef16_all_sources", False
     elif name == "rmat20p":
-        g, wl, prune = gg.workload_rmat20_pendants(), "rmat20_ef16_plus30pct_pendants_pruned", True
+        g, wl, prune = gg.workload_rmat20_pendants(), "rmat20_ef16_plus30pct_pendants_all_sources_pruned", True
     elif name == "grid2048":
         g, wl, prune = gg.workload_roadlike_grid(), "grid2048_roadlike_all_sources", False
     elif name == "strip":
@@ -400,6 +400,9 @@ def main():
     ap.add_argument("--beta", type=float, default=0.0, help="bottom-up switch-back threshold (0 = none)")
     ap.add_argument("--grid-per-cu", type=int, default=0)
     ap.add_argument("--deg2", action="store_true")
+    ap.add_argument("--no-prune", action="store_true",
+                    help="run the scale-20 pendant workload without the 1-degree reduction")
+    ap.add_argument("--prune-trees", action="store_true", help="iterate the 1-degree reduction")
     ap.add_argument("--autotune", type=int, default=-1,
                     help="tune batch/alpha/grid on this many sampled sources first (0 = off; -1 = 4,096 "
                          "when no batch or alpha is given)")
@@ -464,6 +467,12 @@ def main():
               flush=True)
         return
     g, wl, prune, sources = workload(args.config, args.sources)
+    if args.no_prune and prune:
+        prune, wl = False, wl.replace("_pruned", "_unpruned")
+    if args.prune_trees:
+        prune, wl = "trees", wl.replace("_pruned", "") + "_trees"
+    if args.deg2:
+        wl += "_deg2"
     if args.autotune < 0:
         args.autotune = 4096 if (args.batch == 0 and args.alpha is None) else 0
     if args.batch == 0:
@@ -477,14 +486,14 @@ def main():
     ctx = bcm.Context(0)
     G = bcm.Graph(ctx, g, validate=False, prune=prune)
     stream = torch.cuda.Stream()
-    opts = dict(mode=args.mode, batch=args.batch, deg1=prune, deg2=args.deg2, alpha=args.alpha,
+    opts = dict(mode=args.mode, batch=args.batch, deg1=bool(prune), deg2=args.deg2, alpha=args.alpha,
                 grid_per_cu=args.grid_per_cu, beta=args.beta)
     tuned = None
     if args.autotune > 0 and args.mode == "batched":
         import graphgen as gg
         cand = g.non_isolated() if sources is None else sources
         t0 = time.perf_counter()
-        tuned = G.autotune(gg.sample(cand, min(args.autotune, len(cand)), 17), budget_ms=60000.0, deg1=prune,
+        tuned = G.autotune(gg.sample(cand, min(args.autotune, len(cand)), 17), budget_ms=60000.0, deg1=bool(prune),
                            deg2=args.deg2)
         tuned["seconds"] = round(time.perf_counter() - t0, 2)
         log(f"autotune: {tuned}")
@@ -533,15 +542,28 @@ def main():
                      "alg_bytes_per_launch": round(bytes_run / max(st["launches"], 1)),
                      "bytes_per_te": round(bytes_run / st["raw_te"], 3) if st["raw_te"] else None},
     }
+    # heuristics coverage of the graph over all sources (host), as the paper's heuristics table counts it
+    cov = {}
+    for name, kw in (("H0", {}), ("H1", dict(prune=True, deg1=True)), ("H2", dict(deg2=True)),
+                     ("H3", dict(prune=True, deg1=True, deg2=True))):
+        cov[name] = bcm.coverage_host(g.n, g.row_ptr, g.col_idx, **kw)
+    out["coverage"] = cov
     tr = measured_traffic(wl) if args.mode == "batched" else None
     if tr:
+        # HBM bytes from the counters (FETCH_SIZE scaled by a streaming copy's reading, whose
+        # 128-byte requests make the factor an upper bound for the kernel's 32-64-byte sectors;
+        # the raw reading is the lower bound), beside the algorithmic bytes
         out["roofline"]["traffic"] = round(tr["bytes_per_launch"])
+        raw = tr["fetch"]["kernel_bytes_per_launch_raw"] + tr["write"]["kernel_bytes_per_launch_raw"]
+        out["roofline"]["traffic_raw"] = round(raw)
+        out["roofline"]["traffic_GBs"] = round(tr["bytes_per_launch"] / (per_launch_ms / 1e3) / 1e9, 1)
+        out["roofline"]["traffic_raw_GBs"] = round(raw / (per_launch_ms / 1e3) / 1e9, 1)
         out["roofline"]["traffic_source"] = tr["source"]
     if not args.no_plain and args.mode == "batched":
         import graphgen as gg
         cand = g.non_isolated() if sources is None else sources
         ps = gg.sample(cand, min(args.plain_sample, len(cand)), 7)
-        pst, pms = timed_compute(G, ps, stream, mode="plain", deg1=prune)
+        pst, pms = timed_compute(G, ps, stream, mode="plain", deg1=bool(prune))
         pg = pst["te"] / (pms / 1e3) / 1e9
         pbytes = alg_bytes(n, tn, pst["launches"], pst)
         pk = pst["kernel_ms"]
