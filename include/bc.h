@@ -9,8 +9,10 @@
  *     Alg. 2-3) and a successor-checking dependency sweep (Sec. 3.2,
  *     Alg. 4-5);
  *   - optional 1-degree reduction (Sec. 2.2, Eq. (4)-(5); Sec. 3.4.1,
- *     Alg. 6) and 2-degree derivation (Sec. 3.4.2, Lemma 1, Eq. (6),
- *     Alg. 7).
+ *     Alg. 6), also iterated until no tree hangs from the graph (the
+ *     extension the footnote of Sec. 3.4.1 leaves out), and 2-degree
+ *     derivation with the fused backward sweep (Sec. 3.4.2, Lemma 1,
+ *     Eq. (6), Alg. 7-9).
  *
  * Graphs are simple, undirected and unweighted, given as a symmetric CSR
  * (row_ptr[n+1], col_idx[nnz], int32, every pair stored in both directions).
@@ -161,7 +163,11 @@ typedef struct bc_run_stats {
 
 /*
  * Adds the RAW contributions of the given sources to the graph's score
- * array (scores accumulate across calls until bc_scores_reset).
+ * array (scores accumulate across calls until bc_scores_reset): for each
+ * source s, delta_s(v) for every v != s (Eq. (2)), summed as Eq. (3)
+ * prescribes; with BC_H_DEG1 through the reduced graph and Eq. (4)-(5);
+ * each source's forward sweep is Alg. 2-3 and its backward sweep Alg. 4-5,
+ * run one source per launch or 64-1024 per launch.
  *   sources: host array of k original vertex ids, or NULL for every
  *            non-isolated vertex.  Isolated sources contribute nothing.
  *            With BC_H_DEG1 the graph's pruned vertices are handled
@@ -211,8 +217,11 @@ bc_status bc_autotune(bc_graph* g, const int32_t* sample, int64_t k, bc_compute_
                       double* gteps);
 
 enum { BC_RAW = 0, BC_UNDIRECTED = 1 };
-/* Copies the accumulated scores (n doubles) into out (host, or device if
- * out_on_device != 0), optionally halved. */
+/* Copies the accumulated scores (n doubles, the caller's vertex order) into
+ * out (host, or device if out_on_device != 0).  BC_RAW sums over ordered
+ * (source, target) pairs as Eq. (3) does; BC_UNDIRECTED halves it (each
+ * unordered pair once).  Closed-form scores of vertices removed by the
+ * iterated reduction are included. */
 bc_status bc_scores(const bc_graph* g, double* out, int32_t norm, int32_t out_on_device);
 bc_status bc_scores_reset(bc_graph* g);
 

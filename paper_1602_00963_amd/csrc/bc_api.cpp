@@ -627,7 +627,7 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
   r->K = r->B / 64;
   const int blk = r->mode == BC_MODE_BATCHED ? kBatchBlock : 256;
   r->block = o->block ? o->block : blk;
-  if (r->block != blk) return fail(BC_E_INVALID_ARG, "block must be 512 (batched) or 256 (plain)");
+  if (r->block != blk) return fail(BC_E_INVALID_ARG, "block must be 1024 (batched) or 256 (plain, plain_scan)");
   r->grid_per_cu = o->grid_per_cu ? o->grid_per_cu : (g->tuned && !o->batch ? g->tuned_grid : 0);
   r->sigma_mode = o->sigma_mode;
   if (r->sigma_mode < 0 || r->sigma_mode > 2) return fail(BC_E_INVALID_ARG, "unknown sigma mode");
