@@ -65,6 +65,19 @@ def alg_bytes(n: int, nnz: int, launches: int, st: dict) -> float:
     return float(launches * per_launch + 2 * st["reached_nnz"] / 8 + 16 * st["dag_edges"] + 40 * st["reached"])
 
 
+def alg_bytes_wg(n: int, launches: int, st: dict) -> float:
+    """Algorithmic bytes of a per-workgroup run, where every source walks
+    its own scalar state: per sweep and reached vertex its 8-byte row
+    bounds, per sweep and reached directed edge the 4-byte column index and
+    the neighbour's 4-byte level; per DAG edge an 8-byte count forward and
+    an 8-byte dependency term backward; per reached vertex 48 bytes (level
+    written, read and reset 4+4+4, count 8+8+8, dependency 8+8, queue slot
+    4+4 minus the reads counted above as 12); the score array once per
+    launch."""
+    return float(launches * 16 * n + 2 * (8 * st["reached"] + 8 * st["reached_nnz"]) + 16 * st["dag_edges"]
+                 + 48 * st["reached"])
+
+
 def timed_compute(G, sources, stream, **opts):
     import torch
     e0 = torch.cuda.Event(enable_timing=True)
@@ -393,7 +406,11 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="sources per launch (0 = the width measured fastest for the workload: "
                          "1024 on the scale-16 graph, 256 on the others)")
-    ap.add_argument("--mode", default="batched")
+    ap.add_argument("--mode", default=None,
+                    help="batched, plain, plain_scan or per_workgroup (default: per_workgroup on grid2048, "
+                         "batched on the others)")
+    ap.add_argument("--order", default=None,
+                    help="internal vertex order: degree or rcm (default: rcm on grid2048, degree on the others)")
     ap.add_argument("--alpha", type=float, default=None,
                     help="bottom-up threshold (0 = library default, < 0 = never; "
                          "unset = the workload's measured best: -1 on the R-MAT graphs)")
@@ -479,12 +496,16 @@ def main():
         args.batch = BEST_BATCH.get(args.config, 256)
     if args.alpha is None:
         args.alpha = BEST_ALPHA.get(args.config, 0.0)
+    if args.mode is None:
+        args.mode = "per_workgroup" if args.config == "grid2048" else "batched"
+    if args.order is None:
+        args.order = "rcm" if args.config == "grid2048" else "degree"
     if args.plain_sample <= 0:
         args.plain_sample = PLAIN_SAMPLE.get(args.config, 2048)
     n, nnz, m = g.n, g.nnz, g.m
     log(f"workload {wl}: n={n} m={m}")
     ctx = bcm.Context(0)
-    G = bcm.Graph(ctx, g, validate=False, prune=prune)
+    G = bcm.Graph(ctx, g, validate=False, prune=prune, order=args.order)
     stream = torch.cuda.Stream()
     opts = dict(mode=args.mode, batch=args.batch, deg1=bool(prune), deg2=args.deg2, alpha=args.alpha,
                 grid_per_cu=args.grid_per_cu, beta=args.beta)
@@ -520,14 +541,16 @@ def main():
     kern_ms = float(np.median([s["kernel_ms"] for s in stats]))
     per_launch_ms = kern_ms / max(st["launches"], 1)
     tn = nnz if not prune else G.stats()["residual_nnz"]
-    bytes_run = alg_bytes(n, tn, st["launches"], st)
+    bytes_run = (alg_bytes_wg(n, st["launches"], st) if args.mode == "per_workgroup"
+                 else alg_bytes(n, tn, st["launches"], st))
     achieved = bytes_run / (kern_ms / 1e3) / 1e9
     out = {
         "metric": METRIC, "value": round(gteps, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64+f64", "data": "synthetic",
         "config": {"workload": wl, "n": n, "m": m, "sources": int(st["sources"]), "traversed": int(st["traversed"]),
-                   "mode": args.mode, "batch": tuned["batch"] if tuned else args.batch,
+                   "mode": args.mode, "vertex_order": args.order,
+                   "batch": (tuned["batch"] if tuned else args.batch) if args.mode == "batched" else None,
                    "bottom_up_alpha": tuned["alpha"] if tuned else args.alpha,
                    "bottom_up_beta": tuned["beta"] if tuned else args.beta, "pruned": prune,
                    "deg2": args.deg2, "autotuned": tuned},
@@ -535,7 +558,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel_sha": kernel_sha(),
                      "kernel": {"batched": "batch_kernel", "plain": "plain_kernel",
-                                "plain_scan": "scan_kernel"}[args.mode],
+                                "plain_scan": "scan_kernel", "per_workgroup": "wg_kernel"}[args.mode],
                      "avg_launch_ms": round(per_launch_ms, 4), "launches": int(st["launches"]),
                      "kernel_ms_per_step": round(kern_ms, 2), "event_ms_per_step": round(float(np.median(times)), 2),
                      "launch_gap_us": round((float(np.median(times)) - kern_ms) * 1e3 / max(st["launches"], 1), 1),

@@ -77,7 +77,11 @@ enum {
                                 extension the paper's 1-degree section leaves out in a footnote): every
                                 tree hanging from the rest of the graph is folded into the vertex it
                                 hangs from, whole tree components are removed; removed vertices get
-                                closed-form scores on the host (they are cut vertices) */
+                                closed-form scores on the host (they are cut vertices) */,
+  BC_LOAD_ORDER_RCM = 32u    /* renumber internally in reverse Cuthill-McKee order instead of by degree:
+                                neighbours get nearby ids, so a BFS wavefront on a long-diameter graph
+                                (road networks, lattices) touches fewer cache lines; for
+                                BC_MODE_PER_WORKGROUP; ignored with BC_LOAD_KEEP_ORDER */
 };
 
 typedef struct bc_graph_stats {
@@ -109,13 +113,18 @@ bc_status bc_graph_free(bc_graph* g);
 /* ------------------------------------------------------------------ compute */
 
 enum {
-  BC_MODE_PLAIN = 0,    /* one cooperative launch per source */
-  BC_MODE_BATCHED = 1,  /* one cooperative launch per batch of `batch` sources */
-  BC_MODE_PLAIN_SCAN = 2 /* one source per launch with the paper's active-edge mapping (Sec. 3.1):
+  BC_MODE_PLAIN = 0,    /* one persistent launch per source */
+  BC_MODE_BATCHED = 1,  /* one persistent launch per batch of `batch` sources */
+  BC_MODE_PLAIN_SCAN = 2, /* one source per launch with the paper's active-edge mapping (Sec. 3.1):
                             per level a prefix sum of the frontier's degrees and a binary search
                             per edge, the prefix sums reused by the backward sweep; exact counts
                             (wrapped sources are rerun by BC_MODE_PLAIN in extended form), no
                             direction switching, no heuristics; for comparison with BC_MODE_PLAIN */
+  BC_MODE_PER_WORKGROUP = 3 /* one source per workgroup, as many workgroups per CU as fit (grid_per_cu caps it),
+                               levels separated by workgroup barriers only: for long-diameter graphs,
+                               where a device-wide barrier per level dominates and sampled sources
+                               share no frontier a batch could pool; 1-degree reduction supported,
+                               no 2-degree derivation; fp64 score atomics (order-dependent rounding) */
 };
 enum {
   BC_H_DEG1 = 1u,       /* use the graph's 1-degree reduction (needs BC_LOAD_PRUNE_DEG1) */

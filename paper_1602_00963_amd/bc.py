@@ -19,8 +19,8 @@ LIB_PATH = os.path.join(HERE, "libbc.so")
 # status codes (include/bc.h)
 OK, E_INVALID_ARG, E_INVALID_GRAPH, E_OUT_OF_MEMORY, E_DEVICE, E_BUSY, E_NOT_FOUND, E_TIMEOUT, E_REJECTED, \
     E_CAPACITY = range(10)
-LOAD_VALIDATE, LOAD_PRUNE_DEG1, LOAD_DEVICE_PTRS, LOAD_KEEP_ORDER, LOAD_PRUNE_TREES = 1, 2, 4, 8, 16
-MODE_PLAIN, MODE_BATCHED, MODE_PLAIN_SCAN = 0, 1, 2
+LOAD_VALIDATE, LOAD_PRUNE_DEG1, LOAD_DEVICE_PTRS, LOAD_KEEP_ORDER, LOAD_PRUNE_TREES, LOAD_ORDER_RCM = 1, 2, 4, 8, 16, 32
+MODE_PLAIN, MODE_BATCHED, MODE_PLAIN_SCAN, MODE_PER_WORKGROUP = 0, 1, 2, 3
 H_DEG1, H_DEG2 = 1, 2
 SIGMA_AUTO, SIGMA_EXACT_ONLY, SIGMA_EXTENDED = 0, 1, 2
 RAW, UNDIRECTED = 0, 1
@@ -212,7 +212,8 @@ class Context:
 
 def make_opts(mode="batched", batch=256, deg1=False, deg2=False, sigma="auto", alpha=0.0, grid_per_cu=0, beta=0.0):
     o = ComputeOpts()
-    o.mode = {"plain": MODE_PLAIN, "batched": MODE_BATCHED, "plain_scan": MODE_PLAIN_SCAN}[mode]
+    o.mode = {"plain": MODE_PLAIN, "batched": MODE_BATCHED, "plain_scan": MODE_PLAIN_SCAN,
+              "per_workgroup": MODE_PER_WORKGROUP}[mode]
     o.batch = batch
     o.heuristics = (H_DEG1 if deg1 else 0) | (H_DEG2 if deg2 else 0)
     o.sigma_mode = {"auto": SIGMA_AUTO, "exact": SIGMA_EXACT_ONLY, "extended": SIGMA_EXTENDED}[sigma]
@@ -232,14 +233,22 @@ def _stream_handle(stream):
 class Graph:
     """A graph resident in HBM.  `g` is anything with n, row_ptr, col_idx."""
 
-    def __init__(self, ctx: Context, g, validate: bool = True, prune=False, keep_order: bool = False):
+    def __init__(self, ctx: Context, g, validate: bool = True, prune=False, keep_order: bool = False,
+                 order: str = "degree"):
         """prune: False, True (one round of the 1-degree reduction) or "trees"
-        (the reduction iterated until no degree-1 vertex is left)."""
+        (the reduction iterated until no degree-1 vertex is left); order: the
+        internal vertex order, "degree" (decreasing degree) or "rcm" (reverse
+        Cuthill-McKee, for long-diameter graphs); keep_order keeps the
+        caller's."""
         self.ctx = ctx
         self.n = int(g.n)
         self.rp = _i32(g.row_ptr)
         self.ci = _i32(g.col_idx)
         flags = (LOAD_VALIDATE if validate else 0) | (LOAD_KEEP_ORDER if keep_order else 0)
+        if order not in ("degree", "rcm"):
+            raise ValueError(f"unknown vertex order {order!r}")
+        if order == "rcm":
+            flags |= LOAD_ORDER_RCM
         if prune == "trees":
             flags |= LOAD_PRUNE_TREES
         elif prune:

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbc.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["bc_plain.hip", "bc_batch.hip", "bc_scan.hip", "bc_static.hip", "bc_api.cpp", "bc_host.cpp", "bc_server.cpp"]
+SOURCES = ["bc_plain.hip", "bc_batch.hip", "bc_scan.hip", "bc_wg.hip", "bc_static.hip", "bc_api.cpp", "bc_host.cpp", "bc_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -24,7 +24,7 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 7) -> str:
+def build(jobs: int = 8) -> str:
     """Compile every source (always) and link libbc.so."""
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

@@ -15,6 +15,7 @@
 #include "bc_api_internal.h"
 #include "bc_host.h"
 #include "bc_kernels.h"
+#include "bc_wg.h"
 
 using namespace bcx;
 
@@ -135,6 +136,53 @@ size_t scan_layout(int64_t n, char* base, ScanWs* w) {
   t.ovf_count = c.take<int32_t>(1);
   t.stats = c.take<unsigned long long>(kStCount);
   t.bar = c.take<GridBar>(1);
+  c.off = align_up(c.off, 256);
+  t.ctl_bytes = c.off - ctl0;
+  t.ctl_begin = base ? base + ctl0 : nullptr;
+  if (w) *w = t;
+  return c.off;
+}
+
+// Per-workgroup workspace: grid slices of the per-source state, the call's
+// source table, the overflow list and counters.
+struct WgWs {
+  WgVert* vs;
+  int32_t *Q, *qoff, *src, *own, *ovf_list, *ovf_count;
+  double *w, *tsub;
+  unsigned long long* stats;
+  size_t ctl_bytes;
+  char* ctl_begin;
+};
+
+constexpr size_t kWgStateBudget = 64ull << 30;  // bytes of per-workgroup state at most
+
+// Workgroups of the per-workgroup mode: per_cu per compute unit (default:
+// as many as fit), fewer when their state would pass kWgStateBudget.
+int wg_grid(int64_t n, int cus, int per_cu) {
+  int bpc = 1;
+  if (wg_max_grid(&bpc) != hipSuccess || bpc < 1) bpc = 1;
+  const int want = per_cu > 0 ? std::min(per_cu, bpc) : bpc;
+  const size_t per = (sizeof(WgVert) + 8) * (size_t)n + 64;
+  const int64_t fit = (int64_t)std::max<size_t>(1, kWgStateBudget / per);
+  return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * want, fit));
+}
+
+size_t wg_layout(int64_t n, int grid, int64_t nsrc, char* base, WgWs* w) {
+  Carve c{base};
+  WgWs t{};
+  const size_t gn = (size_t)grid * (size_t)n;
+  t.vs = c.take<WgVert>(gn);
+  t.Q = c.take<int32_t>(gn);
+  t.qoff = c.take<int32_t>((size_t)grid * (size_t)(n + 2));
+  t.src = c.take<int32_t>(std::max<int64_t>(nsrc, 1));
+  t.own = c.take<int32_t>(std::max<int64_t>(nsrc, 1));
+  t.w = c.take<double>(std::max<int64_t>(nsrc, 1));
+  t.tsub = c.take<double>(std::max<int64_t>(nsrc, 1));
+  t.ovf_list = c.take<int32_t>(std::max<int64_t>(nsrc, 1));
+  c.off = align_up(c.off, 256);
+  const size_t ctl0 = c.off;
+  t.ovf_count = c.take<int32_t>(1);
+  t.stats = c.take<unsigned long long>(kStCount);
   c.off = align_up(c.off, 256);
   t.ctl_bytes = c.off - ctl0;
   t.ctl_begin = base ? base + ctl0 : nullptr;
@@ -312,12 +360,10 @@ static bc_status upload(const std::vector<T>& h, T** d, int64_t* resident) {
 // vertices touched most often (hubs: every edge to them reads their level
 // masks and counts) then share cache lines at the low ids instead of being
 // spread over the arrays.  perm[caller id] = internal id; rows are re-sorted.
-static void relabel_by_degree(int32_t n, std::vector<int32_t>& rp, std::vector<int32_t>& ci,
-                              std::vector<int32_t>* perm) {
-  std::vector<int32_t> order((size_t)n);
-  for (int32_t v = 0; v < n; ++v) order[v] = v;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+// Rewrites the CSR in the vertex order `order` (order[i] = the vertex placed
+// at position i); perm[v] = position of vertex v.  Rows stay sorted.
+static void relabel(int32_t n, std::vector<int32_t>& rp, std::vector<int32_t>& ci, const std::vector<int32_t>& order,
+                    std::vector<int32_t>* perm) {
   perm->assign((size_t)n, 0);
   for (int32_t i = 0; i < n; ++i) (*perm)[order[i]] = i;
   std::vector<int32_t> nrp((size_t)n + 1, 0), nci(ci.size());
@@ -330,6 +376,69 @@ static void relabel_by_degree(int32_t n, std::vector<int32_t>& rp, std::vector<i
   }
   rp.swap(nrp);
   ci.swap(nci);
+}
+
+// Decreasing degree (stable): hubs first, so their rows and state share lines.
+static std::vector<int32_t> degree_order(int32_t n, const std::vector<int32_t>& rp) {
+  std::vector<int32_t> order((size_t)n);
+  for (int32_t v = 0; v < n; ++v) order[v] = v;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return rp[a + 1] - rp[a] > rp[b + 1] - rp[b]; });
+  return order;
+}
+
+// Reverse Cuthill-McKee: per connected component a breadth-first order from
+// a pseudo-peripheral vertex (George-Liu: repeat a BFS from a least-degree
+// vertex of the last level while the eccentricity grows), neighbours taken
+// by increasing degree; the whole sequence reversed.  Vertices adjacent in
+// the graph land close together, which on long-diameter graphs keeps large
+// runs of a BFS wavefront in consecutive records.
+static std::vector<int32_t> rcm_order(int32_t n, const std::vector<int32_t>& rp, const std::vector<int32_t>& ci) {
+  auto deg = [&](int32_t v) { return rp[v + 1] - rp[v]; };
+  std::vector<int32_t> by_deg((size_t)n);
+  for (int32_t v = 0; v < n; ++v) by_deg[v] = v;
+  std::stable_sort(by_deg.begin(), by_deg.end(), [&](int32_t a, int32_t b) { return deg(a) < deg(b); });
+  std::vector<char> placed((size_t)n, 0);
+  std::vector<int32_t> lvl((size_t)n, -1), q, order, nb;
+  order.reserve((size_t)n);
+  for (int32_t s0 : by_deg) {
+    if (placed[s0]) continue;
+    int32_t root = s0, ecc = -1;
+    for (int it = 0; it < 8; ++it) {  // pseudo-peripheral root
+      q.assign(1, root);
+      lvl[root] = 0;
+      for (size_t h = 0; h < q.size(); ++h)
+        for (int32_t e = rp[q[h]]; e < rp[q[h] + 1]; ++e)
+          if (lvl[ci[e]] < 0) {
+            lvl[ci[e]] = lvl[q[h]] + 1;
+            q.push_back(ci[e]);
+          }
+      const int32_t depth = lvl[q.back()];
+      int32_t best = q.back();
+      for (size_t h = q.size(); h-- > 0 && lvl[q[h]] == depth;)
+        if (deg(q[h]) < deg(best) || (deg(q[h]) == deg(best) && q[h] < best)) best = q[h];
+      for (int32_t v : q) lvl[v] = -1;
+      if (depth <= ecc) break;
+      ecc = depth;
+      root = best;
+    }
+    const size_t start = order.size();
+    order.push_back(root);
+    placed[root] = 1;
+    for (size_t h = start; h < order.size(); ++h) {
+      const int32_t v = order[h];
+      nb.clear();
+      for (int32_t e = rp[v]; e < rp[v + 1]; ++e)
+        if (!placed[ci[e]]) {
+          placed[ci[e]] = 1;
+          nb.push_back(ci[e]);
+        }
+      std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) { return deg(a) != deg(b) ? deg(a) < deg(b) : a < b; });
+      order.insert(order.end(), nb.begin(), nb.end());
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
 }
 
 // Caller ids -> internal ids.
@@ -529,7 +638,9 @@ bc_status bc_graph_load(bc_context* ctx, int32_t n, const int32_t* row_ptr, cons
     g->isolated += dg == 0;
   }
   if (!(flags & BC_LOAD_KEEP_ORDER)) {
-    relabel_by_degree(n, g->h_rp, g->h_ci, &g->perm);
+    const std::vector<int32_t> order =
+        (flags & BC_LOAD_ORDER_RCM) ? rcm_order(n, g->h_rp, g->h_ci) : degree_order(n, g->h_rp);
+    relabel(n, g->h_rp, g->h_ci, order, &g->perm);
     rp = g->h_rp.data();
     ci = g->h_ci.data();
   }
@@ -619,15 +730,17 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
   bc_compute_opts d{};
   if (!o) o = &d;
   r->mode = o->mode;
-  if (r->mode != BC_MODE_PLAIN && r->mode != BC_MODE_BATCHED && r->mode != BC_MODE_PLAIN_SCAN)
+  if (r->mode != BC_MODE_PLAIN && r->mode != BC_MODE_BATCHED && r->mode != BC_MODE_PLAIN_SCAN &&
+      r->mode != BC_MODE_PER_WORKGROUP)
     return fail(BC_E_INVALID_ARG, "unknown mode");
   r->B = o->batch ? o->batch : (g->tuned ? g->tuned_batch : 256);
   if (r->B % 64 != 0 || r->B < 64 || r->B > 64 * kMaxWords)
     return fail(BC_E_INVALID_ARG, "batch must be a multiple of 64 from 64 to 1024");
   r->K = r->B / 64;
-  const int blk = r->mode == BC_MODE_BATCHED ? kBatchBlock : 256;
+  const int blk = (r->mode == BC_MODE_BATCHED || r->mode == BC_MODE_PER_WORKGROUP) ? kBatchBlock : 256;
   r->block = o->block ? o->block : blk;
-  if (r->block != blk) return fail(BC_E_INVALID_ARG, "block must be 1024 (batched) or 256 (plain, plain_scan)");
+  if (r->block != blk)
+    return fail(BC_E_INVALID_ARG, "block must be 1024 (batched, per_workgroup) or 256 (plain, plain_scan)");
   r->grid_per_cu = o->grid_per_cu ? o->grid_per_cu : (g->tuned && !o->batch ? g->tuned_grid : 0);
   r->sigma_mode = o->sigma_mode;
   if (r->sigma_mode < 0 || r->sigma_mode > 2) return fail(BC_E_INVALID_ARG, "unknown sigma mode");
@@ -635,6 +748,7 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
   r->deg2 = (o->heuristics & BC_H_DEG2) != 0;
   if (r->deg1 && !g->pruned) return fail(BC_E_INVALID_ARG, "BC_H_DEG1 needs a graph loaded with BC_LOAD_PRUNE_DEG1");
   if (r->deg2 && r->mode != BC_MODE_BATCHED) return fail(BC_E_INVALID_ARG, "BC_H_DEG2 needs the batched mode");
+  if (r->deg2 && r->mode == BC_MODE_PER_WORKGROUP) return fail(BC_E_INVALID_ARG, "BC_H_DEG2 needs the batched mode");
   if (r->mode == BC_MODE_PLAIN_SCAN && (r->deg1 || r->sigma_mode == BC_SIGMA_EXTENDED))
     return fail(BC_E_INVALID_ARG, "BC_MODE_PLAIN_SCAN takes no heuristics and exact counts");
   if (o->alpha > 0) r->alpha = o->alpha;
@@ -651,6 +765,8 @@ size_t ws_bytes_for(const bc_graph* g, const Resolved& r, int cap_factor) {
   if (r.mode == BC_MODE_PLAIN) return plain_layout(g->n, g->nnz, nullptr, nullptr);
   if (r.mode == BC_MODE_PLAIN_SCAN)  // wrapped sources rerun in the plain workspace
     return std::max(scan_layout(g->n, nullptr, nullptr), plain_layout(g->n, g->nnz, nullptr, nullptr));
+  if (r.mode == BC_MODE_PER_WORKGROUP)  // sized for as many sources as vertices
+    return wg_layout(g->n, wg_grid(g->n, g->ctx->cus, r.grid_per_cu), g->n, nullptr, nullptr);
   return batch_layout(g->n, g->nnz, r.B, cap_factor, r.max_slots, r.trace, nullptr, nullptr);
 }
 
@@ -1160,6 +1276,71 @@ bc_status run_scan(bc_graph* g, const Resolved& r, const TravGraph& tg, const st
   return BC_OK;
 }
 
+// All groups in one launch: each workgroup walks its share of the sources.
+bc_status run_wg(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg, const std::vector<Group>& groups,
+                 char* wsbase, hipStream_t st, double* bc, Exec* ex, CallOut* out) {
+  if (ex) ex->used = 0;
+  const int grid = wg_grid(g->n, g->ctx->cus, r.grid_per_cu);
+  const int64_t ns_all = (int64_t)groups.size();
+  if (ns_all > g->n) {  // the source table holds n groups: run the rest in further launches
+    for (int64_t b = 0; b < ns_all; b += g->n) {
+      const std::vector<Group> part(groups.begin() + b, groups.begin() + std::min<int64_t>(ns_all, b + g->n));
+      CallOut o;
+      bc_status s = run_wg(g, r, ext, tg, part, wsbase, st, bc, ex, &o);
+      if (s != BC_OK) return s;
+      out->merge(o);
+      out->ovf.insert(out->ovf.end(), o.ovf.begin(), o.ovf.end());
+    }
+    return BC_OK;
+  }
+  const int64_t ns = ns_all;
+  WgWs w;
+  wg_layout(g->n, grid, g->n, wsbase, &w);
+  HIPCHK(hipMemsetAsync(w.ctl_begin, 0, w.ctl_bytes, st));
+  HIPCHK(hipMemsetAsync(w.vs, 0, sizeof(WgVert) * (size_t)grid * g->n, st));  // not reached
+  if (ns == 0) return BC_OK;
+  std::vector<int32_t> hs((size_t)ns), ho((size_t)ns);
+  std::vector<double> hw((size_t)ns), ht((size_t)ns);
+  for (int64_t i = 0; i < ns; ++i) {
+    hs[i] = groups[i].v;
+    ho[i] = groups[i].own;
+    hw[i] = groups[i].w;
+    ht[i] = groups[i].tsub;
+  }
+  HIPCHK(hipMemcpyAsync(w.src, hs.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(w.own, ho.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(w.w, hw.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(w.tsub, ht.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st));
+  WgArgs a{};
+  a.n = g->n;
+  a.rp = tg.rp;
+  a.ci = tg.ci;
+  a.omega = tg.omega;
+  a.vs = w.vs;
+  a.Q = w.Q;
+  a.qoff = w.qoff;
+  a.src = w.src;
+  a.w = w.w;
+  a.own = w.own;
+  a.tsub = w.tsub;
+  a.nsrc = ns;
+  a.bc = bc;
+  a.ovf_list = w.ovf_list;
+  a.ovf_count = w.ovf_count;
+  a.stats = w.stats;
+  if (ex) HIPCHK(ex->mark(st));
+  HIPCHK(launch_wg(a, ext, (int)std::min<int64_t>(grid, ns), st));
+  if (ex) HIPCHK(ex->mark(st));
+  int32_t cnt = 0;
+  HIPCHK(hipMemcpyAsync(&cnt, w.ovf_count, sizeof cnt, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(out->st, w.stats, sizeof(out->st), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (ex) HIPCHK(ex->collect(&out->kernel_ms));
+  out->ovf.resize(std::min<int64_t>(cnt, ns));
+  if (cnt) HIPCHK(hipMemcpy(out->ovf.data(), w.ovf_list, sizeof(int32_t) * out->ovf.size(), hipMemcpyDeviceToHost));
+  return BC_OK;
+}
+
 static void add_stats(bc_run_stats* s, const CallOut& o) {
   s->levels += (int64_t)o.st[kStLevels];
   s->bottom_up_levels += (int64_t)o.st[kStBuLevels];
@@ -1208,6 +1389,7 @@ static bc_status run_groups(bc_graph* g, const Resolved& r, bool ext, const Trav
   bc_status s = get_ws(g, ws_bytes_for(g, r, r.cap_factor), user_ws, user_bytes, &ws);
   if (s != BC_OK) return s;
   if (r.mode == BC_MODE_PLAIN_SCAN && !ext) return run_scan(g, r, tg, groups, ws, st, slots[0], ex, out);
+  if (r.mode == BC_MODE_PER_WORKGROUP) return run_wg(g, r, ext, tg, groups, ws, st, slots[0], ex, out);
   if (r.mode == BC_MODE_PLAIN || r.mode == BC_MODE_PLAIN_SCAN) {  // (wrapped scan sources: extended plain form)
     s = run_plain(g, r, ext, tg, groups, ws, st, slots[0], nullptr, ex, out);
     if (s == BC_OK && out->err) return fail(BC_E_CAPACITY, "level-list capacity exceeded");
@@ -1255,7 +1437,8 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
   }
   // AUTO counts probe one word of sources first (below); 2-degree
   // derivation is chosen among the other sources
-  const bool probe = r.mode == BC_MODE_BATCHED && r.sigma_mode == BC_SIGMA_AUTO && groups.size() > (size_t)r.B;
+  const bool probe = (r.mode == BC_MODE_BATCHED || r.mode == BC_MODE_PER_WORKGROUP) && r.sigma_mode == BC_SIGMA_AUTO &&
+                     groups.size() > (size_t)r.B;
   std::vector<Group> rest;
   if (probe) rest.assign(groups.begin() + 64, groups.end());
   if (r.deg2) choose_deg2(g->n, tg.h_rp, tg.h_ci, probe ? rest : groups, &triples);
@@ -1541,7 +1724,8 @@ static bc_status trace_internal(bc_graph* g, const int32_t* sources, int64_t k, 
   if (s != BC_OK) return s;
   if (r.deg1 || (r.deg2 && r.mode != BC_MODE_BATCHED))
     return fail(BC_E_INVALID_ARG, "traces run on the unpruned graph (2-degree derivation: batched only)");
-  if (r.mode == BC_MODE_PLAIN_SCAN) return fail(BC_E_INVALID_ARG, "traces run in the plain or batched mode");
+  if (r.mode == BC_MODE_PLAIN_SCAN || r.mode == BC_MODE_PER_WORKGROUP)
+    return fail(BC_E_INVALID_ARG, "traces run in the plain or batched mode");
   r.trace = true;
   for (int64_t i = 0; i < k; ++i)
     if (sources[i] < 0 || sources[i] >= g->n) return fail(BC_E_INVALID_ARG, "source id out of range");

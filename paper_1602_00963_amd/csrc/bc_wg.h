@@ -1,0 +1,44 @@
+// One source per workgroup (BC_MODE_PER_WORKGROUP): launch arguments and
+// entry points of the per-workgroup kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace bcx {
+
+// Per-source state of one vertex, one 16-byte record so that a neighbour
+// test and its count or dependency share one cache line: lvl = level + 1
+// (0: not reached), e = exponent of the extended count, val = the count
+// (uint64, or the fp64 significand of the extended form) until the backward
+// sweep replaces it with psi = (1 + delta + omega) / sigma (fp64 bits).
+struct alignas(16) WgVert {
+  int32_t lvl;
+  int32_t e;
+  uint64_t val;
+};
+
+// Per-workgroup slices: n vertex records, the stacked level queue (n) and
+// its n + 2 level offsets; the sources and their weights for the launch.
+struct WgArgs {
+  int32_t n;
+  const int32_t* rp;
+  const int32_t* ci;
+  const int32_t* omega;
+  WgVert* vs;                 // [grid][n], all zero between sources
+  int32_t* Q;                 // [grid][n]
+  int32_t* qoff;              // [grid][n + 2]
+  const int32_t* src;         // [nsrc] sources, weights, own counts and subtree sums
+  const double* w;
+  const int32_t* own;
+  const double* tsub;
+  int64_t nsrc;
+  double* bc;
+  int32_t* ovf_list;          // [nsrc] sources whose exact count wrapped
+  int32_t* ovf_count;
+  unsigned long long* stats;  // kSt* counters
+};
+
+hipError_t launch_wg(const WgArgs& a, bool ext, int grid, hipStream_t st);
+hipError_t wg_max_grid(int* blocks_per_cu);  // resident workgroups per CU, both count forms
+
+}  // namespace bcx

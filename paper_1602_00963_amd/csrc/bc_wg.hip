@@ -1,0 +1,191 @@
+// One source per workgroup, many workgroups at once (BC_MODE_PER_WORKGROUP).
+// Every workgroup owns a private copy of the per-source state (one 16-byte
+// record per vertex, the stacked level queue) and walks its sources one
+// after the other; the levels of one source are separated by workgroup
+// barriers only.  On long-diameter graphs (thousands of levels, a few
+// thousand frontier vertices each) a grid-wide barrier per level is what a
+// whole-device launch pays for, and sources spread over the graph share no
+// frontier vertices a batch could pool; here each level costs one workgroup
+// barrier and the device is filled by running hundreds of sources side by
+// side.
+//
+// Forward (Alg. 2-3), one pass per level: threads take frontier vertices;
+// each neighbour still unreached is claimed by an atomic compare-and-swap on
+// its level and appended to the next level.  Exact counts are pushed by
+// atomic 64-bit adds whose returned value exposes a wrap; an extended count
+// (significand, exponent) is pulled by the thread that claimed the vertex,
+// from its neighbours on the current level, whose counts are final.
+// Backward (Alg. 4-5, successor checking): threads take the level's vertices
+// and sum psi = (1 + delta + omega) / sigma over successors; psi replaces the
+// count in the record, which no later step reads.  Scores are added with fp64
+// atomics (order-dependent rounding, within the 1e-9 tolerance).  The
+// touched records are cleared after each source.
+#include "bc_common.h"
+#include "bc_kernels.h"
+#include "bc_wg.h"
+
+namespace bcx {
+
+constexpr int kWgBlock = 1024;
+
+__device__ __forceinline__ double as_f64(uint64_t x) { return __longlong_as_double((long long)x); }
+__device__ __forceinline__ uint64_t as_u64(double x) { return (uint64_t)__double_as_longlong(x); }
+
+template <bool EXT>
+__global__ void __launch_bounds__(kWgBlock) wg_kernel(WgArgs a) {
+  // appends of a level go to counter slot l % 3: the slot of level l + 1 is
+  // cleared at the start of level l, two barriers after its last reader
+  __shared__ int32_t s_cnt[3], s_wrap;
+  __shared__ unsigned long long s_ns, s_rnnz, s_dag;
+  const int32_t n = a.n;
+  const int t = (int)threadIdx.x, nt = (int)blockDim.x;
+  WgVert* __restrict__ V = a.vs + (size_t)blockIdx.x * (size_t)n;
+  int32_t* __restrict__ Q = a.Q + (size_t)blockIdx.x * (size_t)n;
+  int32_t* __restrict__ qoff = a.qoff + (size_t)blockIdx.x * (size_t)(n + 2);
+  const int32_t* __restrict__ rp = a.rp;
+  const int32_t* __restrict__ ci = a.ci;
+  int levels = 0;
+
+  for (int64_t si = blockIdx.x; si < a.nsrc; si += gridDim.x) {
+    const int32_t src = a.src[si];
+    if (t == 0) {
+      V[src].lvl = 1;
+      V[src].e = 0;
+      V[src].val = EXT ? as_u64(1.0) : 1ull;
+      Q[0] = src;
+      qoff[0] = 0;
+      qoff[1] = 1;
+      s_cnt[0] = 0;
+      s_wrap = 0;
+      s_ns = 1 + (a.omega ? (unsigned long long)a.omega[src] : 0ull);
+      s_rnnz = (unsigned long long)(rp[src + 1] - rp[src]);
+      s_dag = 0;
+    }
+    __syncthreads();
+    // ---- forward: level l holds records with lvl == l + 1
+    int32_t l = 0, e0 = 0, e1 = 1;
+    while (e1 > e0) {
+      if (t == 0) s_cnt[(l + 1) % 3] = 0;
+      int32_t* cnt = &s_cnt[l % 3];
+      const int32_t here = l + 1, next = l + 2;
+      unsigned long long ns = 0, rnnz = 0, dag = 0;
+      bool wrap = false;
+      for (int32_t i = e0 + t; i < e1; i += nt) {
+        const int32_t v = Q[i];
+        const uint64_t sv = EXT ? 0ull : V[v].val;
+        const int32_t b = rp[v], end = rp[v + 1];
+        for (int32_t e = b; e < end; ++e) {
+          const int32_t x = ci[e];
+          int32_t dx = V[x].lvl;
+          if (dx == 0) {
+            int32_t expect = 0;
+            if (__hip_atomic_compare_exchange_strong(&V[x].lvl, &expect, next, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP)) {
+              const int32_t pos = atomicAdd(cnt, 1);
+              Q[e1 + pos] = x;
+              dx = next;
+              const int32_t xb = rp[x], xe = rp[x + 1];
+              ns += 1 + (a.omega ? (unsigned long long)a.omega[x] : 0ull);
+              rnnz += (unsigned long long)(xe - xb);
+              if (EXT) {
+                // the new vertex's count, pulled from its neighbours on level l
+                Ext acc = ext_zero();
+                for (int32_t f = xb; f < xe; ++f) {
+                  const WgVert u = V[ci[f]];
+                  if (u.lvl == here) acc = ext_add(acc, Ext{as_f64(u.val), u.e});
+                }
+                const Ext z = ext_norm(acc);
+                V[x].val = as_u64(z.m);
+                V[x].e = z.e;
+              }
+            } else {
+              dx = expect;
+            }
+          }
+          if (dx == next) {
+            dag += 1;
+            if (!EXT) {
+              const uint64_t old = atomicAdd((unsigned long long*)&V[x].val, (unsigned long long)sv);
+              if (old + sv < old) wrap = true;
+            }
+          }
+        }
+      }
+      if (ns) atomicAdd(&s_ns, ns);
+      if (rnnz) atomicAdd(&s_rnnz, rnnz);
+      if (dag) atomicAdd(&s_dag, dag);
+      if (wrap) s_wrap = 1;
+      __syncthreads();
+      const int32_t e2 = e1 + *cnt;
+      if (t == 0) qoff[l + 2] = e2;
+      ++l;
+      e0 = e1;
+      e1 = e2;
+    }
+    __syncthreads();  // qoff of the last level
+    const int32_t depth = l - 1;
+    levels += l;
+    const bool wrapped = s_wrap != 0;
+    // ---- backward (skipped when a count wrapped: the host reruns the source extended)
+    if (!wrapped) {
+      const double wt = a.w[si];
+      for (int32_t lb = depth; lb >= 1; --lb) {
+        const int32_t b0 = qoff[lb], b1 = qoff[lb + 1];
+        const int32_t succ = lb + 2;
+        for (int32_t i = b0 + t; i < b1; i += nt) {
+          const int32_t w = Q[i];
+          const WgVert me = V[w];
+          double acc = 0.0;
+          if (lb < depth) {
+            for (int32_t e = rp[w]; e < rp[w + 1]; ++e) {
+              const WgVert u = V[ci[e]];
+              if (u.lvl == succ) acc += EXT ? ldexp(as_f64(u.val), me.e - u.e) : as_f64(u.val);
+            }
+          }
+          const double sw = EXT ? as_f64(me.val) : (double)me.val;
+          const double delta = sw * acc;
+          const double om = a.omega ? (double)a.omega[w] : 0.0;
+          V[w].val = as_u64((1.0 + delta + om) / sw);
+          const double add = wt * (delta + om);
+          if (add != 0.0) atomicAdd(&a.bc[w], add);
+        }
+        __syncthreads();
+      }
+    }
+    if (t == 0) {
+      if (wrapped) {
+        const int32_t k = atomicAdd(a.ovf_count, 1);
+        a.ovf_list[k] = src;
+      } else if (a.own[si] != 0) {
+        atomicAdd(&a.bc[src], (double)a.own[si] * ((double)s_ns - 1.0) - a.tsub[si]);
+      }
+      atomicAdd(&a.stats[kStReached], (unsigned long long)qoff[depth + 1]);
+      atomicAdd(&a.stats[kStReachedNnz], s_rnnz);
+      atomicAdd(&a.stats[kStDag], s_dag);
+    }
+    // clear what this source touched
+    const int32_t touched = qoff[depth + 1];
+    for (int32_t i = t; i < touched; i += nt) V[Q[i]] = WgVert{0, 0, 0ull};
+    __syncthreads();
+  }
+  if (t == 0) {
+    atomicAdd(&a.stats[kStLevels], (unsigned long long)levels);
+    if (blockIdx.x == 0) atomicAdd(&a.stats[kStLaunches], 1ull);
+  }
+}
+
+hipError_t launch_wg(const WgArgs& a, bool ext, int grid, hipStream_t st) {
+  void* args[] = {(void*)&a};
+  const void* fn = ext ? (const void*)wg_kernel<true> : (const void*)wg_kernel<false>;
+  return hipLaunchKernel(fn, dim3(grid), dim3(kWgBlock), args, 0, st);
+}
+
+hipError_t wg_max_grid(int* blocks_per_cu) {
+  int a = 0, b = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, (const void*)wg_kernel<false>, kWgBlock, 0);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)wg_kernel<true>, kWgBlock, 0);
+  *blocks_per_cu = a < b ? a : b;
+  return e;
+}
+
+}  // namespace bcx

@@ -307,6 +307,53 @@ def test_paper_mapping_mode(bcm, ctx):
         assert st["overflowed"] == int(ovf.sum())
 
 
+def test_per_workgroup_mode(bcm, ctx):
+    """One source per workgroup, hundreds of workgroups at once: the oracle's
+    scores on an R-MAT graph (all sources: several sources per workgroup), a
+    long-diameter road-like strip, closed forms, a union with isolated
+    vertices and repeated sources, and a lattice whose corner counts wrap,
+    with every count form (exact: the wrapped set is the oracle's; extended;
+    auto: wrapped sources rerun extended)."""
+    cases = [(gg.rmat(11, 16, 5), None),
+             (gg.road_grid(300, 4, 0.05, 0.01, 3), None),
+             (gg.path(70), None), (gg.cycle(65), None), (gg.star(40), None), (gg.hypercube(9), None),
+             (gg.disjoint_union(gg.rmat(9, 8, 2), gg.star(7), gg.path(1), gg.cycle(6)),
+              np.array([0, 0, 3, 512, 513, 520, 521, 5], np.int32))]
+    for g, S in cases:
+        say("case per_workgroup", g.name)
+        ref, ovf = oracle.bc(g, S, nthreads=4)
+        got, st = run_bc(bcm, ctx, g, S, mode="per_workgroup")
+        assert_close(got, ref, what=f"per_workgroup {g.name}")
+        assert st["overflowed"] == int(ovf.sum()) == 0
+    g = gg.full_grid(40, 40)
+    S = np.array([0, 39, 1560, 1599, 820, 410, 5 * 40 + 7, 19 * 40 + 21], np.int32)
+    ref, ovf = oracle.bc(g, S)
+    assert ovf.sum() > 0
+    for sm in ["auto", "extended"]:
+        say("case per_workgroup lattice", sm)
+        got, st = run_bc(bcm, ctx, g, S, mode="per_workgroup", sigma=sm)
+        assert_close(got, ref, what=f"per_workgroup lattice {sm}")
+    say("case per_workgroup lattice exact")
+    G = bcm.Graph(ctx, g)
+    st = G.compute(S, mode="per_workgroup", sigma="exact")
+    G.close()
+    assert st["overflowed"] == int(ovf.sum())
+
+
+@pytest.mark.parametrize("prune", [True, "trees"], ids=["deg1", "trees"])
+def test_per_workgroup_pruned(bcm, ctx, prune):
+    """The per-workgroup mode on pruned graphs (one round of 1-degree removal,
+    and the iterated tree reduction): every source, and a sampled subset that
+    includes removed vertices."""
+    g = gg.attach_trees(gg.rmat(11, 8, 7), [1, 1, 2, 3, 5, 9], 4)
+    S = gg.sample(np.arange(g.n), 300, 9)
+    for src in [None, S]:
+        say("case per_workgroup pruned", prune, "all" if src is None else "sample")
+        ref, _ = oracle.bc(g, src, nthreads=4)
+        got, st = run_bc(bcm, ctx, g, src, prune=prune, deg1=True, mode="per_workgroup")
+        assert_close(got, ref, what=f"per_workgroup prune={prune}")
+
+
 def test_sources_with_repeats_and_isolated(bcm, ctx):
     g = gg.disjoint_union(gg.rmat(9, 8, 2), gg.complete(1))
     nz = g.non_isolated()
@@ -437,6 +484,51 @@ def test_roadlike_grid_multi_launch_extended(bcm, ctx):
     got, st = run_bc(bcm, ctx, g, S, mode="batched", batch=256)
     assert ovf.mean() > 0.5 and st["launches"] >= 5, (ovf.mean(), st["launches"])
     assert_close(got, ref, what="grid2048 multi-launch")
+
+
+def test_roadlike_grid_per_workgroup_full_size(bcm, ctx):
+    """The 2048 x 2048 lattice at full size in the benchmark's shape for it:
+    reverse Cuthill-McKee order, one source per workgroup, automatic counts
+    (a one-word probe in exact form that wraps, then extended launches, then
+    the probe's sources rerun extended); scores against the oracle's
+    long-double reruns."""
+    g = gg.workload_roadlike_grid()
+    S = gg.sample(g.non_isolated(), 64 + 300, 37)
+    say("case grid2048 per_workgroup rcm", g.n, g.m)
+    ref, ovf = oracle.bc(g, S, nthreads=16)
+    G = bcm.Graph(ctx, g, validate=False, order="rcm")
+    st = G.compute(S, mode="per_workgroup")
+    got = G.scores()
+    G.close()
+    assert ovf.mean() > 0.5 and st["launches"] >= 3 and st["overflowed"] >= 32, (ovf.mean(), st)
+    assert_close(got, ref, what="grid2048 per_workgroup")
+
+
+@pytest.mark.parametrize("opts", [dict(mode="plain"), dict(mode="batched", batch=128), dict(mode="per_workgroup")],
+                         ids=["plain", "b128", "wg"])
+def test_rcm_vertex_order(bcm, ctx, opts):
+    """Graphs loaded in reverse Cuthill-McKee order give the oracle's scores
+    in caller ids: an R-MAT graph with isolated vertices, a road-like strip,
+    a pruned graph with pendants, and a lattice whose corner counts wrap;
+    traces of the batched form report d and sigma in caller ids."""
+    for g, S, prune in [(gg.disjoint_union(gg.rmat(10, 8, 3), gg.complete(1), gg.path(5)), None, False),
+                        (gg.road_grid(300, 5, 0.05, 0.01, 8), None, False),
+                        (gg.add_pendants(gg.rmat(10, 8, 4), np.random.default_rng(5).integers(0, 1024, 300)), None, True),
+                        (gg.full_grid(40, 40), np.array([0, 39, 1560, 1599, 820, 410], np.int32), False)]:
+        say("case rcm", g.name, opts)
+        ref, _ = oracle.bc(g, S, nthreads=4)
+        G = bcm.Graph(ctx, g, prune=prune, order="rcm")
+        G.compute(S, deg1=prune, **opts)
+        assert_close(G.scores(), ref, what=f"rcm {g.name} {opts}")
+        if opts["mode"] == "batched" and not prune:
+            T = (S if S is not None else g.non_isolated())[:5]
+            tr = G.trace(T, **opts)
+            for i, s in enumerate(T):
+                o = oracle.source(g, int(s))
+                assert np.array_equal(tr["d"][i], o["d"]), s
+                if not o["overflow"]:
+                    assert np.array_equal(tr["sigma"][i], o["sigma"]), s
+        G.close()
 
 
 def test_degree2_derivation_extended_counts(bcm, ctx):
