@@ -90,30 +90,38 @@ def timed_compute(G, sources, stream, **opts):
     return st, e0.elapsed_time(e1)
 
 
-KERNEL_SOURCES = ["paper_1602_00963_amd/csrc/bc_batch.hip", "paper_1602_00963_amd/csrc/bc_common.h",
-                  "paper_1602_00963_amd/csrc/bc_kernels.h"]
+KERNEL_SOURCES = {
+    "batch_kernel": ["paper_1602_00963_amd/csrc/bc_batch.hip", "paper_1602_00963_amd/csrc/bc_common.h",
+                     "paper_1602_00963_amd/csrc/bc_kernels.h"],
+    "wg_kernel": ["paper_1602_00963_amd/csrc/bc_wg.hip", "paper_1602_00963_amd/csrc/bc_wg.h",
+                  "paper_1602_00963_amd/csrc/bc_common.h"],
+}
+MODE_KERNEL = {"batched": "batch_kernel", "plain": "plain_kernel", "plain_scan": "scan_kernel",
+               "per_workgroup": "wg_kernel"}
 
 
-def kernel_sha() -> str:
+def kernel_sha(kernel: str = "batch_kernel") -> str:
     import hashlib
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_name: str):
-    """HBM bytes per launch of the batched kernel from committed rocprofv3
-    counter runs (FETCH_SIZE, WRITE_SIZE, each scaled by the same counter on
-    a plain copy of known size); None unless the kernel source is unchanged
-    since the counters were taken."""
-    p = os.path.join(ROOT, "profiles", f"traffic_batch_kernel_{workload_name}.json")
+def measured_traffic(workload_name: str, kernel: str = "batch_kernel"):
+    """HBM bytes per launch of a kernel from committed rocprofv3 counter
+    runs (FETCH_SIZE, WRITE_SIZE, each scaled by the same counter on a plain
+    copy of known size); None unless the kernel source is unchanged since
+    the counters were taken."""
+    if kernel not in KERNEL_SOURCES:
+        return None
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload_name}.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
         t = json.load(f)
-    if t.get("kernel_sha") != kernel_sha():
+    if t.get("kernel_sha") != kernel_sha(kernel):
         return None
     return t
 
@@ -141,11 +149,12 @@ def _counter_rows(d: str):
         return list(csv.DictReader(fh))
 
 
-def summarize_counters(fetch_dir: str, write_dir: str, wl: str, copy_bytes: int, command: str) -> None:
-    """Per-launch HBM traffic of the batched kernel from two rocprofv3
-    counter runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by
-    what the same counter reads for the copy kernel of known size run in the
-    same process.  Writes profiles/traffic_batch_kernel_<wl>.json and .md."""
+def summarize_counters(fetch_dir: str, write_dir: str, wl: str, copy_bytes: int, command: str,
+                       kernel: str = "batch_kernel") -> None:
+    """Per-launch HBM traffic of a kernel from two rocprofv3 counter runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
+    counter reads for the copy kernel of known size run in the same process.
+    Writes profiles/traffic_<kernel>_<wl>.json and .md."""
     res = {}
     for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         kern, copy = [], []
@@ -153,28 +162,28 @@ def summarize_counters(fetch_dir: str, write_dir: str, wl: str, copy_bytes: int,
             if r["Counter_Name"] != name:
                 continue
             v = float(r["Counter_Value"]) * 1024.0
-            if "batch_kernel" in r["Kernel_Name"]:
+            if kernel in r["Kernel_Name"]:
                 kern.append(v)
             elif "copy" in r["Kernel_Name"].lower() and v > 0.5 * copy_bytes:
                 copy.append(v)
         if not kern or not copy:
-            raise SystemExit(f"{name}: missing batch_kernel or copy dispatches")
+            raise SystemExit(f"{name}: missing {kernel} or copy dispatches")
         scale = copy_bytes / float(np.median(copy))
         res[name] = {"kernel_bytes_per_launch_raw": float(np.mean(kern)), "dispatches": len(kern),
                      "copy_bytes_raw": float(np.median(copy)), "scale": scale,
                      "kernel_bytes_per_launch": float(np.mean(kern)) * scale}
-    t = {"kernel": "batch_kernel", "workload": wl, "kernel_sha": kernel_sha(),
+    t = {"kernel": kernel, "workload": wl, "kernel_sha": kernel_sha(kernel),
          "bytes_per_launch": res["FETCH_SIZE"]["kernel_bytes_per_launch"] + res["WRITE_SIZE"]["kernel_bytes_per_launch"],
          "fetch": res["FETCH_SIZE"], "write": res["WRITE_SIZE"], "copy_bytes": copy_bytes, "command": command,
-         "source": f"profiles/traffic_batch_kernel_{wl}.md"}
+         "source": f"profiles/traffic_{kernel}_{wl}.md"}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
-    with open(os.path.join(ROOT, "profiles", f"traffic_batch_kernel_{wl}.json"), "w") as f:
+    with open(os.path.join(ROOT, "profiles", f"traffic_{kernel}_{wl}.json"), "w") as f:
         json.dump(t, f, indent=1)
-    with open(os.path.join(ROOT, "profiles", f"traffic_batch_kernel_{wl}.md"), "w") as f:
-        f.write(f"# HBM traffic of batch_kernel, workload {wl}\n\n")
+    with open(os.path.join(ROOT, "profiles", f"traffic_{kernel}_{wl}.md"), "w") as f:
+        f.write(f"# HBM traffic of {kernel}, workload {wl}\n\n")
         f.write(f"Counter runs (one per counter, each followed in the same process by a copy of {copy_bytes} bytes):\n\n")
         f.write(f"    {command}\n\n")
-        f.write("| counter | batch_kernel KiB/dispatch (raw) | dispatches | copy raw bytes | scale | bytes/launch |\n")
+        f.write(f"| counter | {kernel} KiB/dispatch (raw) | dispatches | copy raw bytes | scale | bytes/launch |\n")
         f.write("|---|---|---|---|---|---|\n")
         for name in ("FETCH_SIZE", "WRITE_SIZE"):
             r = res[name]
@@ -445,7 +454,7 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="after the run, copy this many bytes (scales the traffic counters)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="write profiles/traffic_batch_kernel_<workload>.json from two counter runs")
+                    help="write profiles/traffic_<kernel>_<workload>.json from two counter runs (the kernel of --mode)")
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR", help="write profiles/<--profile-name>.md")
     ap.add_argument("--profile-name", default="")
     ap.add_argument("--profile-command", default="")
@@ -455,8 +464,9 @@ def main():
         return
     if args.summarize_counters:
         _, wl, _, _ = workload(args.config, args.sources)
+        mode = args.mode or ("per_workgroup" if args.config == "grid2048" else "batched")
         summarize_counters(args.summarize_counters[0], args.summarize_counters[1], wl, args.calibrate_copy,
-                           args.profile_command)
+                           args.profile_command, MODE_KERNEL[mode])
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.profile_name, args.profile_command)
@@ -556,9 +566,10 @@ def main():
                    "deg2": args.deg2, "autotuned": tuned},
         "gteps_2m": round(2 * gteps, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel_sha": kernel_sha(),
-                     "kernel": {"batched": "batch_kernel", "plain": "plain_kernel",
-                                "plain_scan": "scan_kernel", "per_workgroup": "wg_kernel"}[args.mode],
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel_sha": kernel_sha(MODE_KERNEL[args.mode]) if MODE_KERNEL[args.mode] in KERNEL_SOURCES
+                     else None,
+                     "kernel": MODE_KERNEL[args.mode],
                      "avg_launch_ms": round(per_launch_ms, 4), "launches": int(st["launches"]),
                      "kernel_ms_per_step": round(kern_ms, 2), "event_ms_per_step": round(float(np.median(times)), 2),
                      "launch_gap_us": round((float(np.median(times)) - kern_ms) * 1e3 / max(st["launches"], 1), 1),
@@ -571,7 +582,7 @@ def main():
                      ("H3", dict(prune=True, deg1=True, deg2=True))):
         cov[name] = bcm.coverage_host(g.n, g.row_ptr, g.col_idx, **kw)
     out["coverage"] = cov
-    tr = measured_traffic(wl) if args.mode == "batched" else None
+    tr = measured_traffic(wl, MODE_KERNEL[args.mode])
     if tr:
         # HBM bytes from the counters (FETCH_SIZE scaled by a streaming copy's reading, whose
         # 128-byte requests make the factor an upper bound for the kernel's 32-64-byte sectors;
