@@ -304,8 +304,11 @@ __device__ __forceinline__ void forward_unit(const BatchArgs& a, Stage& st, cons
         if (disc) {
           // a neighbour of a level-kl vertex is at distance kl-1, kl or kl+1
           // from the lane's source, so "not yet reached" is "on neither level"
+          // lanes already set at the neighbour (bits only get set within a
+          // level, and the barrier's acquire drops stale lines) need no
+          // atomic: hubs would otherwise take one per frontier edge
           const uint64_t nb = em & ~(px | cur[xk]);
-          if (nb) {
+          if (nb && (nxt[xk] & nb) != nb) {
             const uint64_t old = atomicOr((unsigned long long*)&nxt[xk], (unsigned long long)nb);
             claimed = old == 0ull;
             C.newl += (uint64_t)__popcll(nb & ~old);
@@ -527,7 +530,7 @@ __device__ __forceinline__ void lane_forward_unit(const BatchArgs& a, Stage& st,
     if (td) {
 #pragma unroll
       for (int j = 0; j < Q4; ++j) {
-        if (xv[j] >= 0 && !((px[j] | cx[j]) & bit)) {
+        if (xv[j] >= 0 && !((px[j] | cx[j]) & bit) && !(nxt[(size_t)xv[j] * K + k] & bit)) {
           const size_t xk = (size_t)xv[j] * K + k;
           const uint64_t old = atomicOr((unsigned long long*)&nxt[xk], (unsigned long long)bit);
           if (!(old & bit)) C.newl += 1;

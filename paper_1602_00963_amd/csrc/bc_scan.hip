@@ -56,6 +56,10 @@ __global__ void __launch_bounds__(kScanBlock) scan_kernel(ScanArgs a) {
     a.acc[i] = 0.0;
   }
   if (tid == 0) {
+    // the launch's control words start clear: they are written here, before
+    // the first barrier, because every workgroup reads the overflow flag
+    // after the forward sweep with no barrier before the epilogue
+    *a.ovf_now = 0;
     a.Q[0] = a.src;
     a.qoff[0] = 0;
     a.qoff[1] = 1;
@@ -197,7 +201,8 @@ __global__ void __launch_bounds__(kScanBlock) scan_kernel(ScanArgs a) {
     }
   }
 
-  // ---- epilogue: report a wrapped source, reset the control block
+  // ---- epilogue: report a wrapped source (the next launch clears the
+  // control words itself: a workgroup may still be about to read them here)
   if (tid == 0) {
     if (overflowed) {
       const int32_t k = atomicAdd(a.ovf_count, 1);
@@ -205,8 +210,6 @@ __global__ void __launch_bounds__(kScanBlock) scan_kernel(ScanArgs a) {
     }
     atomicAdd(&a.stats[kStLevels], (unsigned long long)(depth + 1));
     atomicAdd(&a.stats[kStLaunches], 1ull);
-    *a.ovf_now = 0;
-    a.qoff[2] = 0;
   }
 }
 
