@@ -147,7 +147,8 @@ size_t scan_layout(int64_t n, char* base, ScanWs* w) {
 // source table, the overflow list and counters.
 struct WgWs {
   WgVert* vs;
-  int32_t *Q, *qoff, *src, *own, *ovf_list, *ovf_count;
+  int2* Q;
+  int32_t *qoff, *src, *own, *ovf_list, *ovf_count;
   double *w, *tsub;
   unsigned long long* stats;
   size_t ctl_bytes;
@@ -162,7 +163,7 @@ int wg_grid(int64_t n, int cus, int per_cu) {
   int bpc = 1;
   if (wg_max_grid(&bpc) != hipSuccess || bpc < 1) bpc = 1;
   const int want = per_cu > 0 ? std::min(per_cu, bpc) : bpc;
-  const size_t per = (sizeof(WgVert) + 8) * (size_t)n + 64;
+  const size_t per = (sizeof(WgVert) + sizeof(int2) + 4) * (size_t)n + 64;
   const int64_t fit = (int64_t)std::max<size_t>(1, kWgStateBudget / per);
   return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * want, fit));
 }
@@ -172,7 +173,7 @@ size_t wg_layout(int64_t n, int grid, int64_t nsrc, char* base, WgWs* w) {
   WgWs t{};
   const size_t gn = (size_t)grid * (size_t)n;
   t.vs = c.take<WgVert>(gn);
-  t.Q = c.take<int32_t>(gn);
+  t.Q = c.take<int2>(gn);
   t.qoff = c.take<int32_t>((size_t)grid * (size_t)(n + 2));
   t.src = c.take<int32_t>(std::max<int64_t>(nsrc, 1));
   t.own = c.take<int32_t>(std::max<int64_t>(nsrc, 1));
@@ -329,6 +330,9 @@ struct bc_graph {
   // batching order of sources (computed on the first batched call)
   std::vector<int32_t> rank;
   std::once_flag rank_once;
+  std::once_flag ell_once[2];          // packed adjacency of the full / residual graph, built on first use
+  int32_t* d_ell[2] = {nullptr, nullptr};
+  bc_status ell_status[2] = {BC_OK, BC_OK};
   Exec exec;  // launch timing and lane-table staging of calls made under `mu`
   std::mutex mu;
 };
@@ -356,12 +360,8 @@ static bc_status upload(const std::vector<T>& h, T** d, int64_t* resident) {
   return BC_OK;
 }
 
-// Internal vertex order: decreasing degree, ties by the caller's id.  The
-// vertices touched most often (hubs: every edge to them reads their level
-// masks and counts) then share cache lines at the low ids instead of being
-// spread over the arrays.  perm[caller id] = internal id; rows are re-sorted.
 // Rewrites the CSR in the vertex order `order` (order[i] = the vertex placed
-// at position i); perm[v] = position of vertex v.  Rows stay sorted.
+// at position i); perm[caller id] = internal id.  Rows stay sorted.
 static void relabel(int32_t n, std::vector<int32_t>& rp, std::vector<int32_t>& ci, const std::vector<int32_t>& order,
                     std::vector<int32_t>* perm) {
   perm->assign((size_t)n, 0);
@@ -378,7 +378,10 @@ static void relabel(int32_t n, std::vector<int32_t>& rp, std::vector<int32_t>& c
   ci.swap(nci);
 }
 
-// Decreasing degree (stable): hubs first, so their rows and state share lines.
+// The default internal order: decreasing degree, ties by the caller's id.
+// The vertices touched most often (hubs: every edge to them reads their
+// level masks and counts) then share cache lines at the low ids instead of
+// being spread over the arrays.
 static std::vector<int32_t> degree_order(int32_t n, const std::vector<int32_t>& rp) {
   std::vector<int32_t> order((size_t)n);
   for (int32_t v = 0; v < n; ++v) order[v] = v;
@@ -713,7 +716,8 @@ bc_status bc_graph_free(bc_graph* g) {
   if (!g) return BC_OK;
   (void)hipSetDevice(g->ctx->device);
   for (void* p : {(void*)g->d_rp, (void*)g->d_ci, (void*)g->d_rrp, (void*)g->d_rci, (void*)g->d_omega,
-                  (void*)g->d_gu_p, (void*)g->d_gu_b, (void*)g->d_rgu_p, (void*)g->d_rgu_b, (void*)g->d_bc, g->ws})
+                  (void*)g->d_gu_p, (void*)g->d_gu_b, (void*)g->d_rgu_p, (void*)g->d_rgu_b, (void*)g->d_bc,
+                  (void*)g->d_ell[0], (void*)g->d_ell[1], g->ws})
     if (p) (void)hipFree(p);
   g->exec.release();
   delete g;
@@ -1276,6 +1280,34 @@ bc_status run_scan(bc_graph* g, const Resolved& r, const TravGraph& tg, const st
   return BC_OK;
 }
 
+// Packed adjacency for the per-workgroup kernel: kEllWidth ints per vertex,
+// the degree then up to kEllWidth - 1 neighbours in row order, or (larger
+// degree) the row start in the CSR; one aligned 32-byte slot, so a vertex's
+// bounds and (usually) all its neighbours arrive in one line.
+static std::vector<int32_t> build_ell(int32_t n, const int32_t* rp, const int32_t* ci) {
+  std::vector<int32_t> e((size_t)n * kEllWidth, 0);
+  for (int32_t v = 0; v < n; ++v) {
+    int32_t* s = &e[(size_t)v * kEllWidth];
+    const int32_t d = rp[v + 1] - rp[v];
+    s[0] = d;
+    if (d <= kEllWidth - 1) std::copy(ci + rp[v], ci + rp[v + 1], s + 1);
+    else s[1] = rp[v];
+  }
+  return e;
+}
+
+static bc_status ensure_ell(bc_graph* g, bool deg1, const TravGraph& tg, const int32_t** out) {
+  const int i = deg1 ? 1 : 0;
+  std::call_once(g->ell_once[i], [&] {
+    const int32_t* rp = tg.h_rp;
+    const int32_t* ci = tg.h_ci;
+    g->ell_status[i] = upload(build_ell(g->n, rp, ci), &g->d_ell[i], &g->resident);
+  });
+  if (g->ell_status[i] != BC_OK) return g->ell_status[i];
+  *out = g->d_ell[i];
+  return BC_OK;
+}
+
 // All groups in one launch: each workgroup walks its share of the sources.
 bc_status run_wg(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg, const std::vector<Group>& groups,
                  char* wsbase, hipStream_t st, double* bc, Exec* ex, CallOut* out) {
@@ -1313,7 +1345,8 @@ bc_status run_wg(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg, 
   HIPCHK(hipMemcpyAsync(w.tsub, ht.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st));
   WgArgs a{};
   a.n = g->n;
-  a.rp = tg.rp;
+  bc_status es = ensure_ell(g, tg.omega != nullptr, tg, &a.ell);
+  if (es != BC_OK) return es;
   a.ci = tg.ci;
   a.omega = tg.omega;
   a.vs = w.vs;

@@ -6,6 +6,11 @@
 
 namespace bcx {
 
+// Packed adjacency slot per vertex (kEllWidth ints, 32-byte aligned): the
+// degree, then the neighbours in row order when there are at most
+// kEllWidth - 1 of them, else the row's start in the CSR column array.
+constexpr int kEllWidth = 8;
+
 // Per-source state of one vertex, one 16-byte record so that a neighbour
 // test and its count or dependency share one cache line: lvl = level + 1
 // (0: not reached), e = exponent of the extended count, val = the count
@@ -17,15 +22,17 @@ struct alignas(16) WgVert {
   uint64_t val;
 };
 
-// Per-workgroup slices: n vertex records, the stacked level queue (n) and
-// its n + 2 level offsets; the sources and their weights for the launch.
+// Per-workgroup slices: n vertex records, the stacked level queue (n
+// entries of {vertex, successor mask}) and its n + 2 level offsets; the
+// sources and their weights for the launch.
 struct WgArgs {
   int32_t n;
-  const int32_t* rp;
-  const int32_t* ci;
+  const int32_t* ell;         // [n][kEllWidth] packed adjacency
+  const int32_t* ci;          // CSR columns (rows longer than kEllWidth - 1)
   const int32_t* omega;
   WgVert* vs;                 // [grid][n], all zero between sources
-  int32_t* Q;                 // [grid][n]
+  int2* Q;                    // [grid][n]: vertex, and bit j (j < 31) set when the j-th
+                              // neighbour is a successor (bit 31: one at j >= 31)
   int32_t* qoff;              // [grid][n + 2]
   const int32_t* src;         // [nsrc] sources, weights, own counts and subtree sums
   const double* w;

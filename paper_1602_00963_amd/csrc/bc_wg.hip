@@ -11,13 +11,16 @@
 //
 // Forward (Alg. 2-3), one pass per level: threads take frontier vertices;
 // each neighbour still unreached is claimed by an atomic compare-and-swap on
-// its level and appended to the next level.  Exact counts are pushed by
+// its level and appended to the next level, and the frontier entry keeps a
+// mask of which of its neighbours are successors.  Exact counts are pushed by
 // atomic 64-bit adds whose returned value exposes a wrap; an extended count
 // (significand, exponent) is pulled by the thread that claimed the vertex,
 // from its neighbours on the current level, whose counts are final.
 // Backward (Alg. 4-5, successor checking): threads take the level's vertices
-// and sum psi = (1 + delta + omega) / sigma over successors; psi replaces the
-// count in the record, which no later step reads.  Scores are added with fp64
+// and sum psi = (1 + delta + omega) / sigma over the successors the mask
+// names; psi replaces the count in the record, which no later step reads.
+// Adjacency comes from a packed slot per vertex (degree and up to seven
+// neighbours in one 32-byte block), the CSR only for longer rows.  Scores are added with fp64
 // atomics (order-dependent rounding, within the 1e-9 tolerance).  The
 // touched records are cleared after each source.
 #include "bc_common.h"
@@ -27,9 +30,48 @@
 namespace bcx {
 
 constexpr int kWgBlock = 1024;
+constexpr int kEllIn = kEllWidth - 1;  // neighbours held in a slot
 
 __device__ __forceinline__ double as_f64(uint64_t x) { return __longlong_as_double((long long)x); }
 __device__ __forceinline__ uint64_t as_u64(double x) { return (uint64_t)__double_as_longlong(x); }
+
+// A vertex's packed adjacency slot (two 16-byte loads from one 32-byte block).
+struct Adj {
+  int32_t deg;
+  int32_t nb[kEllIn];  // nb[0] is the CSR row start when deg > kEllIn
+};
+
+__device__ __forceinline__ Adj load_adj(const int32_t* __restrict__ ell, int32_t v) {
+  const int4* p = reinterpret_cast<const int4*>(ell) + 2 * (size_t)v;
+  const int4 a = p[0], b = p[1];
+  return Adj{a.x, {a.y, a.z, a.w, b.x, b.y, b.z, b.w}};
+}
+
+// f(j, x) for the neighbours x of a vertex in row order (j = position).
+template <class F>
+__device__ __forceinline__ void for_adj(const Adj& A, const int32_t* __restrict__ ci, F&& f) {
+  if (A.deg <= kEllIn) {
+#pragma unroll
+    for (int j = 0; j < kEllIn; ++j)
+      if (j < A.deg) f(j, A.nb[j]);
+  } else {
+    const int32_t b = A.nb[0];
+    for (int32_t j = 0; j < A.deg; ++j) f(j, ci[b + j]);
+  }
+}
+
+__device__ __forceinline__ uint32_t succ_bit(int32_t j) { return 1u << (j < 31 ? j : 31); }
+
+// Generation tags (extended counts): a record's level word is
+// (generation << kGenShift) | (level + 1), the generation counting the
+// workgroup's sources in the launch; a record of an older generation reads
+// as not reached, so the records need no clearing between sources.  After
+// kGenMax sources the workgroup clears its slice and starts again.  Exact
+// counts are pushed by atomic adds into a record that must start at zero,
+// so that form clears the touched records instead.
+constexpr int kGenShift = 24;
+constexpr int32_t kGenMax = 127;
+constexpr int32_t kLevelMask = (1 << kGenShift) - 1;
 
 template <bool EXT>
 __global__ void __launch_bounds__(kWgBlock) wg_kernel(WgArgs a) {
@@ -40,25 +82,37 @@ __global__ void __launch_bounds__(kWgBlock) wg_kernel(WgArgs a) {
   const int32_t n = a.n;
   const int t = (int)threadIdx.x, nt = (int)blockDim.x;
   WgVert* __restrict__ V = a.vs + (size_t)blockIdx.x * (size_t)n;
-  int32_t* __restrict__ Q = a.Q + (size_t)blockIdx.x * (size_t)n;
+  int2* __restrict__ Q = a.Q + (size_t)blockIdx.x * (size_t)n;
   int32_t* __restrict__ qoff = a.qoff + (size_t)blockIdx.x * (size_t)(n + 2);
-  const int32_t* __restrict__ rp = a.rp;
+  const int32_t* __restrict__ ell = a.ell;
   const int32_t* __restrict__ ci = a.ci;
   int levels = 0;
+  // generations need level + 1 to fit below the tag (no BFS is deeper than n - 1)
+  const bool gens = EXT && n < kLevelMask - 1;
+  int32_t gen = 0;
 
   for (int64_t si = blockIdx.x; si < a.nsrc; si += gridDim.x) {
     const int32_t src = a.src[si];
+    if (gens) {
+      if (gen == kGenMax) {
+        for (int32_t v = t; v < n; v += nt) V[v] = WgVert{0, 0, 0ull};
+        __syncthreads();
+        gen = 0;
+      }
+      ++gen;
+    }
+    const int32_t tag = gens ? gen << kGenShift : 0;  // records with other tags are not reached
     if (t == 0) {
-      V[src].lvl = 1;
+      V[src].lvl = tag | 1;
       V[src].e = 0;
       V[src].val = EXT ? as_u64(1.0) : 1ull;
-      Q[0] = src;
+      Q[0] = make_int2(src, 0);
       qoff[0] = 0;
       qoff[1] = 1;
       s_cnt[0] = 0;
       s_wrap = 0;
       s_ns = 1 + (a.omega ? (unsigned long long)a.omega[src] : 0ull);
-      s_rnnz = (unsigned long long)(rp[src + 1] - rp[src]);
+      s_rnnz = (unsigned long long)ell[(size_t)src * kEllWidth];
       s_dag = 0;
     }
     __syncthreads();
@@ -67,49 +121,58 @@ __global__ void __launch_bounds__(kWgBlock) wg_kernel(WgArgs a) {
     while (e1 > e0) {
       if (t == 0) s_cnt[(l + 1) % 3] = 0;
       int32_t* cnt = &s_cnt[l % 3];
-      const int32_t here = l + 1, next = l + 2;
+      const int32_t here = tag | (l + 1), next = tag | (l + 2);
       unsigned long long ns = 0, rnnz = 0, dag = 0;
       bool wrap = false;
       for (int32_t i = e0 + t; i < e1; i += nt) {
-        const int32_t v = Q[i];
+        const int32_t v = Q[i].x;
         const uint64_t sv = EXT ? 0ull : V[v].val;
-        const int32_t b = rp[v], end = rp[v + 1];
-        for (int32_t e = b; e < end; ++e) {
-          const int32_t x = ci[e];
+        const Adj A = load_adj(ell, v);
+        uint32_t smask = 0;
+        for_adj(A, ci, [&](int32_t j, int32_t x) {
           int32_t dx = V[x].lvl;
-          if (dx == 0) {
-            int32_t expect = 0;
+          bool mine = false;
+          // not reached from this source: claim it; a failed swap returns the
+          // current word, either this level's claim (stop) or an older one
+          // the first read did not see (try again with it)
+          while (gens ? (dx & ~kLevelMask) != tag : dx == 0) {
+            int32_t expect = dx;
             if (__hip_atomic_compare_exchange_strong(&V[x].lvl, &expect, next, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_WORKGROUP)) {
-              const int32_t pos = atomicAdd(cnt, 1);
-              Q[e1 + pos] = x;
+              mine = true;
               dx = next;
-              const int32_t xb = rp[x], xe = rp[x + 1];
-              ns += 1 + (a.omega ? (unsigned long long)a.omega[x] : 0ull);
-              rnnz += (unsigned long long)(xe - xb);
-              if (EXT) {
-                // the new vertex's count, pulled from its neighbours on level l
-                Ext acc = ext_zero();
-                for (int32_t f = xb; f < xe; ++f) {
-                  const WgVert u = V[ci[f]];
-                  if (u.lvl == here) acc = ext_add(acc, Ext{as_f64(u.val), u.e});
-                }
-                const Ext z = ext_norm(acc);
-                V[x].val = as_u64(z.m);
-                V[x].e = z.e;
-              }
-            } else {
-              dx = expect;
+              break;
+            }
+            dx = expect;
+          }
+          if (mine) {
+            const int32_t pos = atomicAdd(cnt, 1);
+            Q[e1 + pos] = make_int2(x, 0);
+            const Adj X = load_adj(ell, x);
+            ns += 1 + (a.omega ? (unsigned long long)a.omega[x] : 0ull);
+            rnnz += (unsigned long long)X.deg;
+            if (EXT) {
+              // the new vertex's count, pulled from its neighbours on level l
+              Ext acc = ext_zero();
+              for_adj(X, ci, [&](int32_t, int32_t u) {
+                const WgVert ru = V[u];
+                if (ru.lvl == here) acc = ext_add(acc, Ext{as_f64(ru.val), ru.e});
+              });
+              const Ext z = ext_norm(acc);
+              V[x].val = as_u64(z.m);
+              V[x].e = z.e;
             }
           }
           if (dx == next) {
             dag += 1;
+            smask |= succ_bit(j);
             if (!EXT) {
               const uint64_t old = atomicAdd((unsigned long long*)&V[x].val, (unsigned long long)sv);
               if (old + sv < old) wrap = true;
             }
           }
-        }
+        });
+        reinterpret_cast<int32_t*>(Q)[2 * (size_t)i + 1] = (int32_t)smask;
       }
       if (ns) atomicAdd(&s_ns, ns);
       if (rnnz) atomicAdd(&s_rnnz, rnnz);
@@ -126,21 +189,26 @@ __global__ void __launch_bounds__(kWgBlock) wg_kernel(WgArgs a) {
     const int32_t depth = l - 1;
     levels += l;
     const bool wrapped = s_wrap != 0;
-    // ---- backward (skipped when a count wrapped: the host reruns the source extended)
+    // ---- backward (skipped when a count wrapped: the host reruns the source
+    // extended); only the neighbours the forward pass marked as successors
     if (!wrapped) {
       const double wt = a.w[si];
       for (int32_t lb = depth; lb >= 1; --lb) {
         const int32_t b0 = qoff[lb], b1 = qoff[lb + 1];
-        const int32_t succ = lb + 2;
+        const int32_t succ = tag | (lb + 2);
         for (int32_t i = b0 + t; i < b1; i += nt) {
-          const int32_t w = Q[i];
+          const int2 qw = Q[i];
+          const int32_t w = qw.x;
+          const uint32_t mask = (uint32_t)qw.y;
           const WgVert me = V[w];
           double acc = 0.0;
-          if (lb < depth) {
-            for (int32_t e = rp[w]; e < rp[w + 1]; ++e) {
-              const WgVert u = V[ci[e]];
-              if (u.lvl == succ) acc += EXT ? ldexp(as_f64(u.val), me.e - u.e) : as_f64(u.val);
-            }
+          if (mask) {
+            const Adj A = load_adj(ell, w);
+            for_adj(A, ci, [&](int32_t j, int32_t u) {
+              if (!(mask & succ_bit(j))) return;
+              const WgVert ru = V[u];
+              if (ru.lvl == succ) acc += EXT ? ldexp(as_f64(ru.val), me.e - ru.e) : as_f64(ru.val);
+            });
           }
           const double sw = EXT ? as_f64(me.val) : (double)me.val;
           const double delta = sw * acc;
@@ -163,9 +231,11 @@ __global__ void __launch_bounds__(kWgBlock) wg_kernel(WgArgs a) {
       atomicAdd(&a.stats[kStReachedNnz], s_rnnz);
       atomicAdd(&a.stats[kStDag], s_dag);
     }
-    // clear what this source touched
-    const int32_t touched = qoff[depth + 1];
-    for (int32_t i = t; i < touched; i += nt) V[Q[i]] = WgVert{0, 0, 0ull};
+    // clear what this source touched (generations: the next tag does it)
+    if (!gens) {
+      const int32_t touched = qoff[depth + 1];
+      for (int32_t i = t; i < touched; i += nt) V[Q[i].x] = WgVert{0, 0, 0ull};
+    }
     __syncthreads();
   }
   if (t == 0) {

@@ -340,6 +340,21 @@ def test_per_workgroup_mode(bcm, ctx):
     assert st["overflowed"] == int(ovf.sum())
 
 
+def test_per_workgroup_many_sources_per_workgroup(bcm, ctx):
+    """Extended counts with more than 127 sources on one workgroup (one
+    workgroup per CU, 33,768 sources): the records' generation tags wrap and
+    the workgroup clears its slice; scores against closed forms (a
+    15-dimensional hypercube and a path of 1,000 vertices)."""
+    d, p = 15, 1000
+    g = gg.disjoint_union(gg.hypercube(d), gg.path(p))
+    say("case per_workgroup generation wrap", g.n)
+    got, st = run_bc(bcm, ctx, g, None, mode="per_workgroup", sigma="extended", grid_per_cu=1)
+    assert st["traversed"] == g.n and g.n > 127 * 256
+    cube = np.full(2 ** d, (d * 2 ** (d - 1) - 2 ** d + 1) / 2)
+    path = np.array([i * (p - 1 - i) for i in range(p)], dtype=float)
+    assert_close(got / 2, np.r_[cube, path], what="generation wrap")
+
+
 @pytest.mark.parametrize("prune", [True, "trees"], ids=["deg1", "trees"])
 def test_per_workgroup_pruned(bcm, ctx, prune):
     """The per-workgroup mode on pruned graphs (one round of 1-degree removal,
