@@ -145,7 +145,7 @@ def _counter_rows(d: str):
     f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if not f:
         raise SystemExit(f"no counter_collection.csv under {d}")
-    with open(f[0]) as fh:
+    with open(max(f, key=os.path.getmtime)) as fh:  # the latest run in the directory
         return list(csv.DictReader(fh))
 
 

@@ -31,8 +31,10 @@ struct WgArgs {
   const int32_t* ci;          // CSR columns (rows longer than kEllWidth - 1)
   const int32_t* omega;
   WgVert* vs;                 // [grid][n], all zero between sources
-  int2* Q;                    // [grid][n]: vertex, and bit j (j < 31) set when the j-th
-                              // neighbour is a successor (bit 31: one at j >= 31)
+  int2* Q;                    // [grid][n]: vertex and a neighbour mask: bit j (j < 31) for
+                              // the j-th neighbour being a predecessor (extended counts,
+                              // from the pull) until the vertex's claim pass, a successor
+                              // after it (bit 31: a successor at some j >= 31)
   int32_t* qoff;              // [grid][n + 2]
   const int32_t* src;         // [nsrc] sources, weights, own counts and subtree sums
   const double* w;

@@ -125,11 +125,14 @@ __global__ void __launch_bounds__(kWgBlock) wg_kernel(WgArgs a) {
       unsigned long long ns = 0, rnnz = 0, dag = 0;
       bool wrap = false;
       for (int32_t i = e0 + t; i < e1; i += nt) {
-        const int32_t v = Q[i].x;
+        const int2 qv = Q[i];
+        const int32_t v = qv.x;
+        const uint32_t pmask = (uint32_t)qv.y;  // predecessors found when v's count was pulled
         const uint64_t sv = EXT ? 0ull : V[v].val;
         const Adj A = load_adj(ell, v);
         uint32_t smask = 0;
         for_adj(A, ci, [&](int32_t j, int32_t x) {
+          if (j < 31 && ((pmask >> j) & 1u)) return;  // on level l - 1: neither claimable nor a successor
           int32_t dx = V[x].lvl;
           bool mine = false;
           // not reached from this source: claim it; a failed swap returns the
@@ -147,21 +150,26 @@ __global__ void __launch_bounds__(kWgBlock) wg_kernel(WgArgs a) {
           }
           if (mine) {
             const int32_t pos = atomicAdd(cnt, 1);
-            Q[e1 + pos] = make_int2(x, 0);
             const Adj X = load_adj(ell, x);
             ns += 1 + (a.omega ? (unsigned long long)a.omega[x] : 0ull);
             rnnz += (unsigned long long)X.deg;
+            uint32_t pm = 0;
             if (EXT) {
               // the new vertex's count, pulled from its neighbours on level l
+              // (its predecessors, remembered for its own claim pass)
               Ext acc = ext_zero();
-              for_adj(X, ci, [&](int32_t, int32_t u) {
+              for_adj(X, ci, [&](int32_t jx, int32_t u) {
                 const WgVert ru = V[u];
-                if (ru.lvl == here) acc = ext_add(acc, Ext{as_f64(ru.val), ru.e});
+                if (ru.lvl == here) {
+                  acc = ext_add(acc, Ext{as_f64(ru.val), ru.e});
+                  if (jx < 31) pm |= 1u << jx;
+                }
               });
               const Ext z = ext_norm(acc);
               V[x].val = as_u64(z.m);
               V[x].e = z.e;
             }
+            Q[e1 + pos] = make_int2(x, (int32_t)pm);
           }
           if (dx == next) {
             dag += 1;
@@ -172,7 +180,7 @@ __global__ void __launch_bounds__(kWgBlock) wg_kernel(WgArgs a) {
             }
           }
         });
-        reinterpret_cast<int32_t*>(Q)[2 * (size_t)i + 1] = (int32_t)smask;
+        reinterpret_cast<int32_t*>(Q)[2 * (size_t)i + 1] = (int32_t)smask;  // now the successors
       }
       if (ns) atomicAdd(&s_ns, ns);
       if (rnnz) atomicAdd(&s_rnnz, rnnz);
