@@ -78,6 +78,27 @@ def alg_bytes_wg(n: int, launches: int, st: dict) -> float:
                  + 48 * st["reached"])
 
 
+def stream_copy_gbs(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Achievable HBM bandwidth: a device-to-device copy of nbytes timed with
+    HIP events (median of reps), counted as bytes read plus bytes written."""
+    import torch
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (float(np.median(ts)) / 1e3) / 1e9
+
+
 def timed_compute(G, sources, stream, **opts):
     import torch
     e0 = torch.cuda.Event(enable_timing=True)
@@ -576,6 +597,10 @@ def main():
                      "alg_bytes_per_launch": round(bytes_run / max(st["launches"], 1)),
                      "bytes_per_te": round(bytes_run / st["raw_te"], 3) if st["raw_te"] else None},
     }
+    copy_gbs = stream_copy_gbs()
+    out["roofline"]["stream_copy_GBs"] = round(copy_gbs, 1)
+    out["roofline"]["frac_of_stream_copy"] = round(achieved / copy_gbs, 4)
+    log(f"streaming copy: {copy_gbs:.0f} GB/s")
     # heuristics coverage of the graph over all sources (host), as the paper's heuristics table counts it
     cov = {}
     for name, kw in (("H0", {}), ("H1", dict(prune=True, deg1=True)), ("H2", dict(deg2=True)),

@@ -473,6 +473,21 @@ def test_roadlike_grid_full_size_sampled(bcm, ctx):
     assert_close(got, ref, what="grid2048")
 
 
+def test_rmat_pendants_recipe_scale14_all_sources(bcm, ctx):
+    """The scale-20 workload's recipe at scale 14 (R-MAT EF 16, seed 3, plus
+    30% pendants, seed 33), every source, in the benchmark's launch shape
+    (128 sources per launch, top-down only): pruned and unpruned runs both
+    equal the oracle over all sources."""
+    g = gg.workload_rmat20_pendants(scale=14)
+    say("case rmat14 pendants all sources", g.n, g.m)
+    ref, _ = oracle.bc(g, nthreads=16)
+    got_p, st_p = run_bc(bcm, ctx, g, None, prune=True, deg1=True, mode="batched", batch=128, alpha=-1.0)
+    got_u, st_u = run_bc(bcm, ctx, g, None, mode="batched", batch=128, alpha=-1.0)
+    assert st_p["traversed"] < st_u["traversed"] and st_p["sources"] == st_u["sources"]
+    assert_close(got_p, ref, what="rmat14 pendants pruned")
+    assert_close(got_u, ref, what="rmat14 pendants unpruned")
+
+
 def test_rmat_scale20_pendants_multi_launch(bcm, ctx):
     """The scale-20 graph with pendants, pruned, in the benchmark's tuned
     launch shape (128 sources per launch, top-down only) over several
