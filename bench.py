@@ -437,8 +437,8 @@ def main():
                     help="sources per launch (0 = the width measured fastest for the workload: "
                          "1024 on the scale-16 graph, 256 on the others)")
     ap.add_argument("--mode", default=None,
-                    help="batched, plain, plain_scan or per_workgroup (default: per_workgroup on grid2048, "
-                         "batched on the others)")
+                    help="batched, plain, plain_scan, per_workgroup or auto (default: per_workgroup on "
+                         "grid2048, batched on the others)")
     ap.add_argument("--order", default=None,
                     help="internal vertex order: degree or rcm (default: rcm on grid2048, degree on the others)")
     ap.add_argument("--alpha", type=float, default=None,
@@ -572,7 +572,8 @@ def main():
     kern_ms = float(np.median([s["kernel_ms"] for s in stats]))
     per_launch_ms = kern_ms / max(st["launches"], 1)
     tn = nnz if not prune else G.stats()["residual_nnz"]
-    bytes_run = (alg_bytes_wg(n, st["launches"], st) if args.mode == "per_workgroup"
+    mode_run = st["mode"]  # the mode the library ran (resolves "auto")
+    bytes_run = (alg_bytes_wg(n, st["launches"], st) if mode_run == "per_workgroup"
                  else alg_bytes(n, tn, st["launches"], st))
     achieved = bytes_run / (kern_ms / 1e3) / 1e9
     out = {
@@ -580,17 +581,17 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64+f64", "data": "synthetic",
         "config": {"workload": wl, "n": n, "m": m, "sources": int(st["sources"]), "traversed": int(st["traversed"]),
-                   "mode": args.mode, "vertex_order": args.order,
-                   "batch": (tuned["batch"] if tuned else args.batch) if args.mode == "batched" else None,
+                   "mode": mode_run, "vertex_order": args.order,
+                   "batch": (tuned["batch"] if tuned else args.batch) if mode_run == "batched" else None,
                    "bottom_up_alpha": tuned["alpha"] if tuned else args.alpha,
                    "bottom_up_beta": tuned["beta"] if tuned else args.beta, "pruned": prune,
                    "deg2": args.deg2, "autotuned": tuned},
         "gteps_2m": round(2 * gteps, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel_sha": kernel_sha(MODE_KERNEL[args.mode]) if MODE_KERNEL[args.mode] in KERNEL_SOURCES
+                     "kernel_sha": kernel_sha(MODE_KERNEL[mode_run]) if MODE_KERNEL[mode_run] in KERNEL_SOURCES
                      else None,
-                     "kernel": MODE_KERNEL[args.mode],
+                     "kernel": MODE_KERNEL[mode_run],
                      "avg_launch_ms": round(per_launch_ms, 4), "launches": int(st["launches"]),
                      "kernel_ms_per_step": round(kern_ms, 2), "event_ms_per_step": round(float(np.median(times)), 2),
                      "launch_gap_us": round((float(np.median(times)) - kern_ms) * 1e3 / max(st["launches"], 1), 1),
@@ -607,7 +608,7 @@ def main():
                      ("H3", dict(prune=True, deg1=True, deg2=True))):
         cov[name] = bcm.coverage_host(g.n, g.row_ptr, g.col_idx, **kw)
     out["coverage"] = cov
-    tr = measured_traffic(wl, MODE_KERNEL[args.mode])
+    tr = measured_traffic(wl, MODE_KERNEL[mode_run])
     if tr:
         # HBM bytes from the counters (FETCH_SIZE scaled by a streaming copy's reading, whose
         # 128-byte requests make the factor an upper bound for the kernel's 32-64-byte sectors;
@@ -618,7 +619,7 @@ def main():
         out["roofline"]["traffic_GBs"] = round(tr["bytes_per_launch"] / (per_launch_ms / 1e3) / 1e9, 1)
         out["roofline"]["traffic_raw_GBs"] = round(raw / (per_launch_ms / 1e3) / 1e9, 1)
         out["roofline"]["traffic_source"] = tr["source"]
-    if not args.no_plain and args.mode == "batched":
+    if not args.no_plain and mode_run == "batched":
         import graphgen as gg
         cand = g.non_isolated() if sources is None else sources
         ps = gg.sample(cand, min(args.plain_sample, len(cand)), 7)

@@ -96,6 +96,8 @@ typedef struct bc_graph_stats {
   int64_t max_degree;
   int64_t resident_bytes;  /* device bytes held by the graph (CSR, G', omega, scores) */
   int64_t tree_vertices;   /* vertices removed by the iterated reduction (BC_LOAD_PRUNE_TREES) */
+  int64_t bfs_depth;       /* levels of a breadth-first search from a highest-degree vertex (a lower
+                              bound on the diameter; chooses the kernel under BC_MODE_AUTO) */
 } bc_graph_stats;
 
 /*
@@ -124,7 +126,10 @@ enum {
                                levels separated by workgroup barriers only: for long-diameter graphs,
                                where a device-wide barrier per level dominates and sampled sources
                                share no frontier a batch could pool; 1-degree reduction supported,
-                               no 2-degree derivation; fp64 score atomics (order-dependent rounding) */
+                               no 2-degree derivation; fp64 score atomics (order-dependent rounding) */,
+  BC_MODE_AUTO = 4          /* BC_MODE_PER_WORKGROUP when the graph's bfs_depth (bc_graph_stats) exceeds
+                               64 and BC_H_DEG2 is not requested, else BC_MODE_BATCHED; the mode run is
+                               reported in bc_run_stats.mode */
 };
 enum {
   BC_H_DEG1 = 1u,       /* use the graph's 1-degree reduction (needs BC_LOAD_PRUNE_DEG1) */
@@ -168,6 +173,7 @@ typedef struct bc_run_stats {
   double ms;                /* wall time of the call, host-measured, ms */
   double kernel_ms;         /* sum of the kernel launches' durations, timed with HIP events
                                recorded on the call's stream around each launch, ms */
+  int64_t mode;             /* the mode run (BC_MODE_AUTO resolved) */
 } bc_run_stats;
 
 /*

@@ -20,7 +20,9 @@ LIB_PATH = os.path.join(HERE, "libbc.so")
 OK, E_INVALID_ARG, E_INVALID_GRAPH, E_OUT_OF_MEMORY, E_DEVICE, E_BUSY, E_NOT_FOUND, E_TIMEOUT, E_REJECTED, \
     E_CAPACITY = range(10)
 LOAD_VALIDATE, LOAD_PRUNE_DEG1, LOAD_DEVICE_PTRS, LOAD_KEEP_ORDER, LOAD_PRUNE_TREES, LOAD_ORDER_RCM = 1, 2, 4, 8, 16, 32
-MODE_PLAIN, MODE_BATCHED, MODE_PLAIN_SCAN, MODE_PER_WORKGROUP = 0, 1, 2, 3
+MODE_PLAIN, MODE_BATCHED, MODE_PLAIN_SCAN, MODE_PER_WORKGROUP, MODE_AUTO = 0, 1, 2, 3, 4
+MODE_NAMES = {MODE_PLAIN: "plain", MODE_BATCHED: "batched", MODE_PLAIN_SCAN: "plain_scan",
+              MODE_PER_WORKGROUP: "per_workgroup", MODE_AUTO: "auto"}
 H_DEG1, H_DEG2 = 1, 2
 SIGMA_AUTO, SIGMA_EXACT_ONLY, SIGMA_EXTENDED = 0, 1, 2
 RAW, UNDIRECTED = 0, 1
@@ -35,7 +37,7 @@ EXPORTED = ["bc_context_create", "bc_context_destroy", "bc_graph_load", "bc_grap
 class GraphStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in ("n", "m", "nnz", "isolated", "pendants", "k2_vertices",
                                                  "residual_nnz", "deg2_vertices", "max_degree", "resident_bytes",
-                                                 "tree_vertices")]
+                                                 "tree_vertices", "bfs_depth")]
 
 
 class ComputeOpts(ctypes.Structure):
@@ -50,11 +52,13 @@ class RunStats(ctypes.Structure):
                 ("first_overflow", ctypes.c_int32 * 8), ("levels", ctypes.c_int64),
                 ("bottom_up_levels", ctypes.c_int64), ("reached", ctypes.c_int64), ("reached_nnz", ctypes.c_int64),
                 ("dag_edges", ctypes.c_int64), ("launches", ctypes.c_int64), ("te", ctypes.c_double),
-                ("raw_te", ctypes.c_double), ("ms", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
+                ("raw_te", ctypes.c_double), ("ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("mode", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
         d["first_overflow"] = [x for x in self.first_overflow if x >= 0]
+        d["mode"] = MODE_NAMES.get(self.mode, str(self.mode))
         return d
 
 
@@ -212,8 +216,7 @@ class Context:
 
 def make_opts(mode="batched", batch=256, deg1=False, deg2=False, sigma="auto", alpha=0.0, grid_per_cu=0, beta=0.0):
     o = ComputeOpts()
-    o.mode = {"plain": MODE_PLAIN, "batched": MODE_BATCHED, "plain_scan": MODE_PLAIN_SCAN,
-              "per_workgroup": MODE_PER_WORKGROUP}[mode]
+    o.mode = {v: k for k, v in MODE_NAMES.items()}[mode]
     o.batch = batch
     o.heuristics = (H_DEG1 if deg1 else 0) | (H_DEG2 if deg2 else 0)
     o.sigma_mode = {"auto": SIGMA_AUTO, "exact": SIGMA_EXACT_ONLY, "extended": SIGMA_EXTENDED}[sigma]

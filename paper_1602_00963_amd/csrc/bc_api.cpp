@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -315,8 +316,9 @@ struct bc_graph {
   int2 *d_gu_p = nullptr, *d_gu_b = nullptr, *d_rgu_p = nullptr, *d_rgu_b = nullptr;
   int32_t ngu_p = 0, ngu_b = 0, nrgu_p = 0, nrgu_b = 0;
   double* d_bc = nullptr;
-  int64_t resident = 0;
+  std::atomic<int64_t> resident{0};  // device bytes held (read by bc_graph_stats_get without the lock)
   int64_t max_degree = 0, isolated = 0, pendants = 0, k2 = 0, deg2 = 0, rnnz = 0, tree = 0;
+  int64_t bfs_depth = 0;  // eccentricity of a highest-degree vertex (a lower bound on the diameter)
   // scores of the vertices removed by the iterated reduction (host, internal
   // order), accumulated like the device scores until bc_scores_reset
   std::vector<double> h_tree;
@@ -330,9 +332,8 @@ struct bc_graph {
   // batching order of sources (computed on the first batched call)
   std::vector<int32_t> rank;
   std::once_flag rank_once;
-  std::once_flag ell_once[2];          // packed adjacency of the full / residual graph, built on first use
+  std::mutex ell_mu;                   // packed adjacency of the full / residual graph, built on first use
   int32_t* d_ell[2] = {nullptr, nullptr};
-  bc_status ell_status[2] = {BC_OK, BC_OK};
   Exec exec;  // launch timing and lane-table staging of calls made under `mu`
   std::mutex mu;
 };
@@ -352,12 +353,27 @@ static std::vector<int2> static_units(int32_t n, const int32_t* rp, int chunk) {
 }
 
 template <class T>
-static bc_status upload(const std::vector<T>& h, T** d, int64_t* resident) {
+static bc_status upload(const std::vector<T>& h, T** d, std::atomic<int64_t>* resident) {
   const size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
   HIPCHK(hipMalloc((void**)d, bytes));
   if (!h.empty()) HIPCHK(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   *resident += (int64_t)bytes;
   return BC_OK;
+}
+
+// Number of levels below v in a breadth-first search from v.
+static int64_t bfs_depth_from(int32_t n, const int32_t* rp, const int32_t* ci, int32_t v) {
+  std::vector<int32_t> lvl((size_t)n, -1), q;
+  q.reserve((size_t)n);
+  q.push_back(v);
+  lvl[v] = 0;
+  for (size_t h = 0; h < q.size(); ++h)
+    for (int32_t e = rp[q[h]]; e < rp[q[h] + 1]; ++e)
+      if (lvl[ci[e]] < 0) {
+        lvl[ci[e]] = lvl[q[h]] + 1;
+        q.push_back(ci[e]);
+      }
+  return lvl[q.back()];
 }
 
 // Rewrites the CSR in the vertex order `order` (order[i] = the vertex placed
@@ -635,11 +651,14 @@ bc_status bc_graph_load(bc_context* ctx, int32_t n, const int32_t* row_ptr, cons
     delete g;
     return fail(BC_E_INVALID_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
   }
+  int32_t hub = 0;
   for (int32_t v = 0; v < n; ++v) {
     const int64_t dg = rp[v + 1] - rp[v];
+    if (dg > g->max_degree) hub = v;
     g->max_degree = std::max(g->max_degree, dg);
     g->isolated += dg == 0;
   }
+  g->bfs_depth = bfs_depth_from(n, rp, ci, hub);
   if (!(flags & BC_LOAD_KEEP_ORDER)) {
     const std::vector<int32_t> order =
         (flags & BC_LOAD_ORDER_RCM) ? rcm_order(n, g->h_rp, g->h_ci) : degree_order(n, g->h_rp);
@@ -708,7 +727,8 @@ bc_status bc_graph_stats_get(const bc_graph* g, bc_graph_stats* out) {
   out->deg2_vertices = g->deg2;
   out->max_degree = g->max_degree;
   out->tree_vertices = g->tree;
-  out->resident_bytes = g->resident;
+  out->bfs_depth = g->bfs_depth;
+  out->resident_bytes = g->resident.load();
   return BC_OK;
 }
 
@@ -730,10 +750,17 @@ bc_status bc_graph_free(bc_graph* g) {
 
 namespace bcx {
 
+// BC_MODE_AUTO: graphs whose breadth-first depth from a highest-degree
+// vertex exceeds this run one source per workgroup (R-MAT graphs stay near
+// ten levels, road networks and lattices reach hundreds to thousands).
+constexpr int64_t kLongDepth = 64;
+
 static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* r) {
   bc_compute_opts d{};
   if (!o) o = &d;
   r->mode = o->mode;
+  if (r->mode == BC_MODE_AUTO)  // long diameters (thousands of levels) go one source per workgroup
+    r->mode = (g->bfs_depth > kLongDepth && !(o->heuristics & BC_H_DEG2)) ? BC_MODE_PER_WORKGROUP : BC_MODE_BATCHED;
   if (r->mode != BC_MODE_PLAIN && r->mode != BC_MODE_BATCHED && r->mode != BC_MODE_PLAIN_SCAN &&
       r->mode != BC_MODE_PER_WORKGROUP)
     return fail(BC_E_INVALID_ARG, "unknown mode");
@@ -1298,12 +1325,16 @@ static std::vector<int32_t> build_ell(int32_t n, const int32_t* rp, const int32_
 
 static bc_status ensure_ell(bc_graph* g, bool deg1, const TravGraph& tg, const int32_t** out) {
   const int i = deg1 ? 1 : 0;
-  std::call_once(g->ell_once[i], [&] {
-    const int32_t* rp = tg.h_rp;
-    const int32_t* ci = tg.h_ci;
-    g->ell_status[i] = upload(build_ell(g->n, rp, ci), &g->d_ell[i], &g->resident);
-  });
-  if (g->ell_status[i] != BC_OK) return g->ell_status[i];
+  std::lock_guard<std::mutex> lk(g->ell_mu);
+  if (!g->d_ell[i]) {  // a failed build leaves it null, and the next call tries again
+    int32_t* d = nullptr;
+    const bc_status s = upload(build_ell(g->n, tg.h_rp, tg.h_ci), &d, &g->resident);
+    if (s != BC_OK) {
+      if (d) (void)hipFree(d);
+      return s;
+    }
+    g->d_ell[i] = d;
+  }
   *out = g->d_ell[i];
   return BC_OK;
 }
@@ -1533,6 +1564,7 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
   }
   rs.raw_te = (double)rs.traversed * (double)(tg.nnz / 2);
   rs.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  rs.mode = r.mode;
   if (stats) *stats = rs;
   return BC_OK;
 }

@@ -355,6 +355,28 @@ def test_per_workgroup_many_sources_per_workgroup(bcm, ctx):
     assert_close(got / 2, np.r_[cube, path], what="generation wrap")
 
 
+def test_auto_mode_choice(bcm, ctx):
+    """BC_MODE_AUTO runs a long-diameter graph (a road-like strip, about 300
+    levels from its highest-degree vertex) one source per workgroup and a
+    small-world graph (R-MAT, a handful of levels) batched, and both give the
+    oracle's scores; with 2-degree derivation requested it stays batched."""
+    for g, want in [(gg.road_grid(300, 4, 0.05, 0.01, 3), "per_workgroup"), (gg.rmat(11, 16, 5), "batched")]:
+        say("case auto mode", g.name)
+        S = gg.sample(g.non_isolated(), 400, 13)
+        ref, _ = oracle.bc(g, S, nthreads=4)
+        G = bcm.Graph(ctx, g)
+        depth = G.stats()["bfs_depth"]
+        st = G.compute(S, mode="auto")
+        assert st["mode"] == want, (g.name, depth, st["mode"])
+        assert (depth > 64) == (want == "per_workgroup"), depth
+        assert_close(G.scores(), ref, what=f"auto {g.name}")
+        G.reset()
+        st2 = G.compute(S, mode="auto", deg2=True)
+        assert st2["mode"] == "batched"
+        assert_close(G.scores(), ref, what=f"auto deg2 {g.name}")
+        G.close()
+
+
 @pytest.mark.parametrize("prune", [True, "trees"], ids=["deg1", "trees"])
 def test_per_workgroup_pruned(bcm, ctx, prune):
     """The per-workgroup mode on pruned graphs (one round of 1-degree removal,
