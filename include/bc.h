@@ -149,7 +149,11 @@ typedef struct bc_compute_opts {
   double alpha;         /* bottom-up when frontier edges * alpha > unvisited edges; 0 = default
                            (tuned if available, else 1 batched / 4 plain), < 0 = never bottom-up */
   int32_t block;        /* threads per workgroup: 0, or the mode's fixed size (1024 batched, 256 plain) */
-  int32_t grid_per_cu;  /* workgroups per CU for the persistent grid; 0 = occupancy limit */
+  int32_t grid_per_cu;  /* workgroups per CU for the persistent grid; 0 = the library's choice
+                           (batched: one; plain: four when the traversed graph has at least 2^24
+                           directed edges, else one; per-workgroup: as many as fit); persistent
+                           grids are capped one below the occupancy query's limit, whose last
+                           workgroup per CU was not always resident */
   double beta;          /* switch back: a bottom-up sweep stays bottom-up until the frontier holds
                            fewer than n / beta vertices (batched: (vertex, word) entries against
                            n * words); 0 = no hysteresis (tuned if available), each level tests alpha */

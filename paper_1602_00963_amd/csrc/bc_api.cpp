@@ -818,12 +818,23 @@ static TravGraph trav(const bc_graph* g, bool deg1) {
                    g->h_rp.data(), g->h_ci.data()};
 }
 
+// Plain-form graphs with at least this many traversed directed edges run
+// four workgroups per CU (wide levels hide more latency), smaller ones one
+// (fewer workgroups make the per-level barrier cheaper); measured on the
+// scale-16 (1 best) and scale-20 (4-6 best) R-MAT graphs.
+constexpr int64_t kPlainWideNnz = int64_t(1) << 24;
+
 static int grid_for(const bc_graph* g, const Resolved& r, bool ext, bool batched) {
   int bpc = 1;
   hipError_t e = batched ? batch_max_grid(ext, r.block, &bpc) : plain_max_grid(ext, r.block, &bpc);
   if (e != hipSuccess || bpc < 1) bpc = 1;
-  int want = r.grid_per_cu > 0 ? r.grid_per_cu : (batched ? bpc : 1);
-  const int grid = g->ctx->cus * std::min(want, bpc);
+  // The occupancy query's last workgroup per CU did not always fit beside the
+  // others (the plain kernel at 7 per CU never became wholly resident, and a
+  // persistent grid that is not cannot pass its first barrier): stay below it.
+  const int cap = bpc > 1 ? bpc - 1 : 1;
+  const int64_t tnnz = r.deg1 ? g->rnnz : g->nnz;
+  const int want = r.grid_per_cu > 0 ? r.grid_per_cu : (batched ? cap : (tnnz >= kPlainWideNnz ? 4 : 1));
+  const int grid = g->ctx->cus * std::min(want, cap);
   return r.grid_total > 0 ? std::min(grid, r.grid_total) : grid;
 }
 
