@@ -649,18 +649,22 @@ def test_rmat_scale16_hub_sources_traced(bcm, ctx):
         assert_close(tr["delta"][i], dl, what=f"delta of source {s}")
 
 
-def test_device_score_output_and_workspace(bcm, ctx):
+@pytest.mark.parametrize("opts", [dict(mode="batched", batch=128), dict(mode="per_workgroup"),
+                                  dict(mode="per_workgroup", sigma="extended")], ids=["b128", "wg", "wg_ext"])
+def test_device_score_output_and_workspace(bcm, ctx, opts):
+    """A caller-owned workspace of bc_workspace_size bytes (filled with
+    garbage first) and a caller stream; scores written to a device tensor."""
     import torch
-    g = gg.rmat(9, 8, 3)
+    g = gg.disjoint_union(gg.rmat(9, 8, 3), gg.road_grid(40, 3, 0.05, 0.01, 2))
     ref, _ = oracle.bc(g)
     G = bcm.Graph(ctx, g)
-    nbytes = G.workspace_size(mode="batched", batch=128)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    nbytes = G.workspace_size(**opts)
+    ws = torch.full((nbytes,), 0xA5, dtype=torch.uint8, device="cuda")
     s = torch.cuda.Stream()
-    G.compute(None, workspace=ws, stream=s, mode="batched", batch=128)
+    G.compute(None, workspace=ws, stream=s, **opts)
     out = torch.zeros(g.n, dtype=torch.float64, device="cuda")
     G.scores("undirected", out=out)
-    assert_close(out.cpu().numpy() * 2, ref, what="device output")
+    assert_close(out.cpu().numpy() * 2, ref, what=f"device output {opts}")
     G.close()
 
 
