@@ -129,7 +129,9 @@ enum {
                                no 2-degree derivation; fp64 score atomics (order-dependent rounding) */,
   BC_MODE_AUTO = 4          /* BC_MODE_PER_WORKGROUP when the graph's bfs_depth (bc_graph_stats) exceeds
                                64 and BC_H_DEG2 is not requested, else BC_MODE_BATCHED; the mode run is
-                               reported in bc_run_stats.mode */
+                               reported in bc_run_stats.mode.  (With BC_SIGMA_AUTO, in these two modes,
+                               once a probe of 64 sources on a graph finds most counts wrapping, later
+                               calls on that graph start in the extended form.) */
 };
 enum {
   BC_H_DEG1 = 1u,       /* use the graph's 1-degree reduction (needs BC_LOAD_PRUNE_DEG1) */
@@ -305,9 +307,11 @@ bc_status bc_coverage_host(int32_t n, const int32_t* row_ptr, const int32_t* col
 typedef struct bc_server_config {
   int64_t hbm_budget_bytes;  /* device bytes the server may hold at once (workspaces and result
                                 arrays); 0 = 64 GiB */
-  int32_t max_inflight;      /* concurrent batches (streams); 0 = 4.  Each batch's persistent
-                                grid is a 1/max_inflight share of the device's resident
-                                workgroups, so the running batches co-run on the device */
+  int32_t max_inflight;      /* concurrent batches (streams); 0 = 4.  Each batch's grid is a
+                                1/max_inflight share of the device's resident workgroups, so the
+                                running batches co-run on the device.  Batches run in
+                                BC_MODE_AUTO: graphs deeper than 64 levels one source per
+                                workgroup, the others batched */
   int32_t batch;             /* sources per batch, multiple of 64 up to 256; 0 = 256 */
   int32_t queue_capacity;    /* pending queries; 0 = 4096 */
   uint32_t heuristics;       /* 0, or BC_H_DEG1: queries on graphs loaded with

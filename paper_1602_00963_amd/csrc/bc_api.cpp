@@ -151,6 +151,7 @@ struct WgWs {
   int2* Q;
   int32_t *qoff, *src, *own, *ovf_list, *ovf_count;
   double *w, *tsub;
+  double** sbc;  // per source: the score array its contributions go to
   unsigned long long* stats;
   size_t ctl_bytes;
   char* ctl_begin;
@@ -160,13 +161,15 @@ constexpr size_t kWgStateBudget = 64ull << 30;  // bytes of per-workgroup state 
 
 // Workgroups of the per-workgroup mode: per_cu per compute unit (default:
 // as many as fit), fewer when their state would pass kWgStateBudget.
-int wg_grid(int64_t n, int cus, int per_cu) {
+int wg_grid(int64_t n, int cus, int per_cu, int total) {
   int bpc = 1;
   if (wg_max_grid(&bpc) != hipSuccess || bpc < 1) bpc = 1;
   const int want = per_cu > 0 ? std::min(per_cu, bpc) : bpc;
   const size_t per = (sizeof(WgVert) + sizeof(int2) + 4) * (size_t)n + 64;
   const int64_t fit = (int64_t)std::max<size_t>(1, kWgStateBudget / per);
-  return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * want, fit));
+  int64_t grid = std::min<int64_t>((int64_t)cus * want, fit);
+  if (total > 0) grid = std::min<int64_t>(grid, total);  // a server worker's share
+  return (int)std::max<int64_t>(1, grid);
 }
 
 size_t wg_layout(int64_t n, int grid, int64_t nsrc, char* base, WgWs* w) {
@@ -180,6 +183,7 @@ size_t wg_layout(int64_t n, int grid, int64_t nsrc, char* base, WgWs* w) {
   t.own = c.take<int32_t>(std::max<int64_t>(nsrc, 1));
   t.w = c.take<double>(std::max<int64_t>(nsrc, 1));
   t.tsub = c.take<double>(std::max<int64_t>(nsrc, 1));
+  t.sbc = c.take<double*>(std::max<int64_t>(nsrc, 1));
   t.ovf_list = c.take<int32_t>(std::max<int64_t>(nsrc, 1));
   c.off = align_up(c.off, 256);
   const size_t ctl0 = c.off;
@@ -332,6 +336,7 @@ struct bc_graph {
   // batching order of sources (computed on the first batched call)
   std::vector<int32_t> rank;
   std::once_flag rank_once;
+  std::atomic<bool> ext_hint{false};   // an exact-count probe on this graph found most sources wrapping
   std::mutex ell_mu;                   // packed adjacency of the full / residual graph, built on first use
   int32_t* d_ell[2] = {nullptr, nullptr};
   Exec exec;  // launch timing and lane-table staging of calls made under `mu`
@@ -797,7 +802,7 @@ size_t ws_bytes_for(const bc_graph* g, const Resolved& r, int cap_factor) {
   if (r.mode == BC_MODE_PLAIN_SCAN)  // wrapped sources rerun in the plain workspace
     return std::max(scan_layout(g->n, nullptr, nullptr), plain_layout(g->n, g->nnz, nullptr, nullptr));
   if (r.mode == BC_MODE_PER_WORKGROUP)  // sized for as many sources as vertices
-    return wg_layout(g->n, wg_grid(g->n, g->ctx->cus, r.grid_per_cu), g->n, nullptr, nullptr);
+    return wg_layout(g->n, wg_grid(g->n, g->ctx->cus, r.grid_per_cu, r.grid_total), g->n, nullptr, nullptr);
   return batch_layout(g->n, g->nnz, r.B, cap_factor, r.max_slots, r.trace, nullptr, nullptr);
 }
 
@@ -1352,15 +1357,15 @@ static bc_status ensure_ell(bc_graph* g, bool deg1, const TravGraph& tg, const i
 
 // All groups in one launch: each workgroup walks its share of the sources.
 bc_status run_wg(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg, const std::vector<Group>& groups,
-                 char* wsbase, hipStream_t st, double* bc, Exec* ex, CallOut* out) {
+                 char* wsbase, hipStream_t st, double* const* slots, int nslots, Exec* ex, CallOut* out) {
   if (ex) ex->used = 0;
-  const int grid = wg_grid(g->n, g->ctx->cus, r.grid_per_cu);
+  const int grid = wg_grid(g->n, g->ctx->cus, r.grid_per_cu, r.grid_total);
   const int64_t ns_all = (int64_t)groups.size();
   if (ns_all > g->n) {  // the source table holds n groups: run the rest in further launches
     for (int64_t b = 0; b < ns_all; b += g->n) {
       const std::vector<Group> part(groups.begin() + b, groups.begin() + std::min<int64_t>(ns_all, b + g->n));
       CallOut o;
-      bc_status s = run_wg(g, r, ext, tg, part, wsbase, st, bc, ex, &o);
+      bc_status s = run_wg(g, r, ext, tg, part, wsbase, st, slots, nslots, ex, &o);
       if (s != BC_OK) return s;
       out->merge(o);
       out->ovf.insert(out->ovf.end(), o.ovf.begin(), o.ovf.end());
@@ -1375,12 +1380,16 @@ bc_status run_wg(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg, 
   if (ns == 0) return BC_OK;
   std::vector<int32_t> hs((size_t)ns), ho((size_t)ns);
   std::vector<double> hw((size_t)ns), ht((size_t)ns);
+  std::vector<double*> hb((size_t)ns);
   for (int64_t i = 0; i < ns; ++i) {
     hs[i] = groups[i].v;
     ho[i] = groups[i].own;
     hw[i] = groups[i].w;
     ht[i] = groups[i].tsub;
+    if (groups[i].slot < 0 || groups[i].slot >= nslots) return fail(BC_E_INVALID_ARG, "source group without a result slot");
+    hb[i] = slots[groups[i].slot];
   }
+  HIPCHK(hipMemcpyAsync(w.sbc, hb.data(), sizeof(double*) * ns, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(w.src, hs.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(w.own, ho.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(w.w, hw.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st));
@@ -1399,7 +1408,7 @@ bc_status run_wg(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg, 
   a.own = w.own;
   a.tsub = w.tsub;
   a.nsrc = ns;
-  a.bc = bc;
+  a.sbc = w.sbc;
   a.ovf_list = w.ovf_list;
   a.ovf_count = w.ovf_count;
   a.stats = w.stats;
@@ -1464,7 +1473,7 @@ static bc_status run_groups(bc_graph* g, const Resolved& r, bool ext, const Trav
   bc_status s = get_ws(g, ws_bytes_for(g, r, r.cap_factor), user_ws, user_bytes, &ws);
   if (s != BC_OK) return s;
   if (r.mode == BC_MODE_PLAIN_SCAN && !ext) return run_scan(g, r, tg, groups, ws, st, slots[0], ex, out);
-  if (r.mode == BC_MODE_PER_WORKGROUP) return run_wg(g, r, ext, tg, groups, ws, st, slots[0], ex, out);
+  if (r.mode == BC_MODE_PER_WORKGROUP) return run_wg(g, r, ext, tg, groups, ws, st, slots, nslots, ex, out);
   if (r.mode == BC_MODE_PLAIN || r.mode == BC_MODE_PLAIN_SCAN) {  // (wrapped scan sources: extended plain form)
     s = run_plain(g, r, ext, tg, groups, ws, st, slots[0], nullptr, ex, out);
     if (s == BC_OK && out->err) return fail(BC_E_CAPACITY, "level-list capacity exceeded");
@@ -1512,8 +1521,13 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
   }
   // AUTO counts probe one word of sources first (below); 2-degree
   // derivation is chosen among the other sources
-  const bool probe = (r.mode == BC_MODE_BATCHED || r.mode == BC_MODE_PER_WORKGROUP) && r.sigma_mode == BC_SIGMA_AUTO &&
-                     groups.size() > (size_t)r.B;
+  // (once a probe on this graph has found most counts wrapping, later calls
+  // go to the extended form directly)
+  const bool auto_counts =
+      (r.mode == BC_MODE_BATCHED || r.mode == BC_MODE_PER_WORKGROUP) && r.sigma_mode == BC_SIGMA_AUTO;
+  const bool hinted = auto_counts && g->ext_hint.load();
+  const bool probe = auto_counts && !hinted &&
+                     groups.size() > (size_t)(r.mode == BC_MODE_PER_WORKGROUP ? 64 : r.B);
   std::vector<Group> rest;
   if (probe) rest.assign(groups.begin() + 64, groups.end());
   if (r.deg2) choose_deg2(g->n, tg.h_rp, tg.h_ci, probe ? rest : groups, &triples);
@@ -1523,7 +1537,17 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
   rs.traversed = (int64_t)groups.size() - (int64_t)triples.size();
   rs.derived = (int64_t)triples.size();
   rs.te = (double)credited * (double)(g->nnz / 2);
-  bool ext0 = r.sigma_mode == BC_SIGMA_EXTENDED;
+  bool ext0 = r.sigma_mode == BC_SIGMA_EXTENDED || hinted;
+  // extended batches on such graphs: worst-case lists, batches narrow enough
+  // for them (when the library owns the workspace)
+  auto worst_case = [&](Resolved* q) {
+    if (workspace || q->mode != BC_MODE_BATCHED) return;
+    q->cap_factor = 64;
+    while (q->B > 64 && (int64_t)g->n * q->B + 1024 > (int64_t)INT32_MAX / 2) {
+      q->B /= 2;
+      q->K = q->B / 64;
+    }
+  };
   CallOut co;
   bc_status s = BC_OK;
   if (probe) {
@@ -1542,13 +1566,8 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
     if (s != BC_OK) return s;
     if (2 * co.ovf.size() > head.size()) {
       ext0 = true;
-      if (!workspace) {
-        rr.cap_factor = 64;
-        while (rr.B > 64 && (int64_t)g->n * rr.B + 1024 > (int64_t)INT32_MAX / 2) {
-          rr.B /= 2;
-          rr.K = rr.B / 64;
-        }
-      }
+      g->ext_hint.store(true);
+      worst_case(&rr);
     }
     CallOut c2;
     s = run_groups(g, rr, ext0, tg, rest, triples, workspace, ws_bytes, st, slots, nslots, ex, &c2);
@@ -1556,7 +1575,9 @@ bc_status compute_groups(bc_graph* g, const Resolved& r, std::vector<Group>& gro
     co.merge(c2);
     co.ovf.insert(co.ovf.end(), c2.ovf.begin(), c2.ovf.end());
   } else {
-    s = run_groups(g, r, ext0, tg, groups, triples, workspace, ws_bytes, st, slots, nslots, ex, &co);
+    Resolved rh = r;
+    if (hinted) worst_case(&rh);
+    s = run_groups(g, rh, ext0, tg, groups, triples, workspace, ws_bytes, st, slots, nslots, ex, &co);
     if (s != BC_OK) return s;
   }
   add_stats(&rs, co);

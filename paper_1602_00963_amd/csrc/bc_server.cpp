@@ -119,7 +119,7 @@ namespace {
 
 bc_compute_opts serve_opts(const bc_server* s, const bc_graph* g) {
   bc_compute_opts o{};
-  o.mode = BC_MODE_BATCHED;
+  o.mode = BC_MODE_AUTO;  // long-diameter graphs run one source per workgroup
   o.batch = s->cfg.batch;
   o.sigma_mode = BC_SIGMA_AUTO;
   o.heuristics = ((s->cfg.heuristics & BC_H_DEG1) && graph_pruned(g)) ? BC_H_DEG1 : 0u;

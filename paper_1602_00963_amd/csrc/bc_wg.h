@@ -41,7 +41,7 @@ struct WgArgs {
   const int32_t* own;
   const double* tsub;
   int64_t nsrc;
-  double* bc;
+  double* const* sbc;         // [nsrc] the score array each source's contributions go to
   int32_t* ovf_list;          // [nsrc] sources whose exact count wrapped
   int32_t* ovf_count;
   unsigned long long* stats;  // kSt* counters

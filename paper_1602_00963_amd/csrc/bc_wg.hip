@@ -199,6 +199,7 @@ __global__ void __launch_bounds__(kWgBlock) wg_kernel(WgArgs a) {
     const bool wrapped = s_wrap != 0;
     // ---- backward (skipped when a count wrapped: the host reruns the source
     // extended); only the neighbours the forward pass marked as successors
+    double* __restrict__ bc = a.sbc[si];  // the result array of the source's query
     if (!wrapped) {
       const double wt = a.w[si];
       for (int32_t lb = depth; lb >= 1; --lb) {
@@ -223,7 +224,7 @@ __global__ void __launch_bounds__(kWgBlock) wg_kernel(WgArgs a) {
           const double om = a.omega ? (double)a.omega[w] : 0.0;
           V[w].val = as_u64((1.0 + delta + om) / sw);
           const double add = wt * (delta + om);
-          if (add != 0.0) atomicAdd(&a.bc[w], add);
+          if (add != 0.0) atomicAdd(&bc[w], add);
         }
         __syncthreads();
       }
@@ -233,7 +234,7 @@ __global__ void __launch_bounds__(kWgBlock) wg_kernel(WgArgs a) {
         const int32_t k = atomicAdd(a.ovf_count, 1);
         a.ovf_list[k] = src;
       } else if (a.own[si] != 0) {
-        atomicAdd(&a.bc[src], (double)a.own[si] * ((double)s_ns - 1.0) - a.tsub[si]);
+        atomicAdd(&bc[src], (double)a.own[si] * ((double)s_ns - 1.0) - a.tsub[si]);
       }
       atomicAdd(&a.stats[kStReached], (unsigned long long)qoff[depth + 1]);
       atomicAdd(&a.stats[kStReachedNnz], s_rnnz);

@@ -66,6 +66,35 @@ def test_mix_equals_alone(bcm, ctx):
         G.close()
 
 
+def test_serving_long_diameter_graph(bcm, ctx):
+    """A road-like strip (hundreds of levels: the server runs it one source
+    per workgroup) served beside an R-MAT graph (batched): every query equals
+    the oracle, and on an 80 x 80 lattice (most counts wrap 64 bits) the jobs
+    after the first exact-count probe go to extended counts directly."""
+    graphs = [gg.road_grid(300, 4, 0.05, 0.01, 3), gg.rmat(10, 8, 101), gg.full_grid(80, 80)]
+    Gs = [bcm.Graph(ctx, g) for g in graphs]
+    assert Gs[0].stats()["bfs_depth"] > 64 and Gs[2].stats()["bfs_depth"] > 64 and Gs[1].stats()["bfs_depth"] <= 64
+    rng = np.random.default_rng(9)
+    queries = []
+    for i in range(12):
+        gi = i % len(graphs)
+        cand = graphs[gi].non_isolated()
+        k = int(rng.integers(30, min(400, len(cand))))
+        queries.append((gi, gg.sample(cand, k, 3000 + i)))
+    say("case serving long diameter: submit", len(queries))
+    srv = bcm.Server(ctx, max_inflight=3, batch=256)
+    tickets = [srv.submit(Gs[gi], S) for gi, S in queries]
+    for t in tickets:
+        srv.wait(t)
+    srv.close()
+    for (gi, S), t in zip(queries, tickets):
+        ref, _ = oracle.bc(graphs[gi], S, nthreads=4)
+        ok = oracle.close(t.out, ref, 1e-9)
+        assert ok.all(), (gi, len(S), np.nonzero(~ok)[0][:5])
+    for G in Gs:
+        G.close()
+
+
 def test_submit_from_threads(bcm, ctx):
     g = gg.rmat(10, 16, 7)
     G = bcm.Graph(ctx, g)
