@@ -171,11 +171,13 @@ def _counter_rows(d: str):
 
 
 def summarize_counters(fetch_dir: str, write_dir: str, wl: str, copy_bytes: int, command: str,
-                       kernel: str = "batch_kernel") -> None:
+                       kernel: str = "batch_kernel", last: int = 0) -> None:
     """Per-launch HBM traffic of a kernel from two rocprofv3 counter runs
     (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
     counter reads for the copy kernel of known size run in the same process.
-    Writes profiles/traffic_<kernel>_<wl>.json and .md."""
+    With last > 0 only the kernel's last `last` dispatches count (the timed
+    step's, after warm-up launches of other sizes).  Writes
+    profiles/traffic_<kernel>_<wl>.json and .md."""
     res = {}
     for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         kern, copy = [], []
@@ -184,11 +186,14 @@ def summarize_counters(fetch_dir: str, write_dir: str, wl: str, copy_bytes: int,
                 continue
             v = float(r["Counter_Value"]) * 1024.0
             if kernel in r["Kernel_Name"]:
-                kern.append(v)
+                kern.append((int(r.get("Dispatch_Id") or 0), v))
             elif "copy" in r["Kernel_Name"].lower() and v > 0.5 * copy_bytes:
                 copy.append(v)
         if not kern or not copy:
             raise SystemExit(f"{name}: missing {kernel} or copy dispatches")
+        kern = [v for _, v in sorted(kern)]  # dispatch order
+        if last > 0:
+            kern = kern[-last:]
         scale = copy_bytes / float(np.median(copy))
         res[name] = {"kernel_bytes_per_launch_raw": float(np.mean(kern)), "dispatches": len(kern),
                      "copy_bytes_raw": float(np.median(copy)), "scale": scale,
@@ -234,6 +239,23 @@ def summarize_trace(trace_dir: str, name: str, command: str) -> None:
             fo.write(f"| `{short}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
                      f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |\n")
+        # kernels dispatched only a few times: every dispatch, in order (launches
+        # of different sizes - a probe, a rerun - then stay apart from the step's)
+        tf = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+        if tf:
+            with open(max(tf, key=os.path.getmtime)) as fh:
+                disp = [d for d in csv.DictReader(fh) if "bcx::" in d["Kernel_Name"]]
+            by = {}
+            for d in disp:
+                by.setdefault(d["Kernel_Name"], []).append((int(d["Start_Timestamp"]),
+                                                            (int(d["End_Timestamp"]) - int(d["Start_Timestamp"])) / 1e6,
+                                                            d["Grid_Size_X"]))
+            few = {k: v for k, v in by.items() if len(v) <= 12}
+            if few:
+                fo.write("\nDispatches in order (ms, grid threads):\n\n")
+                for k, v in few.items():
+                    short = k if len(k) < 70 else k[:67] + "..."
+                    fo.write(f"- `{short}`: " + ", ".join(f"{ms:.2f} ({grid})" for _, ms, grid in sorted(v)) + "\n")
     print(open(out).read())
 
 
@@ -478,6 +500,8 @@ def main():
                     help="write profiles/traffic_<kernel>_<workload>.json from two counter runs (the kernel of --mode)")
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR", help="write profiles/<--profile-name>.md")
     ap.add_argument("--profile-name", default="")
+    ap.add_argument("--counter-last", type=int, default=0,
+                    help="with --summarize-counters: count only the kernel's last N dispatches")
     ap.add_argument("--profile-command", default="")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -487,7 +511,7 @@ def main():
         _, wl, _, _ = workload(args.config, args.sources)
         mode = args.mode or ("per_workgroup" if args.config == "grid2048" else "batched")
         summarize_counters(args.summarize_counters[0], args.summarize_counters[1], wl, args.calibrate_copy,
-                           args.profile_command, MODE_KERNEL[mode])
+                           args.profile_command, MODE_KERNEL[mode], args.counter_last)
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.profile_name, args.profile_command)
