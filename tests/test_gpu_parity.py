@@ -405,7 +405,8 @@ def test_sources_with_repeats_and_isolated(bcm, ctx):
         assert st["traversed"] == len(set(int(s) for s in S if deg[s] > 0))
 
 
-@pytest.mark.parametrize("opts", MODES[:3], ids=MODE_IDS[:3])
+@pytest.mark.parametrize("opts", MODES[:3] + [dict(mode="per_workgroup"), dict(mode="auto")],
+                         ids=MODE_IDS[:3] + ["wg", "auto"])
 def test_degenerate_inputs(bcm, ctx, opts):
     """One vertex, only isolated vertices, an empty source list, a 2-vertex
     component under pruning, and a ragged last batch (130 sources)."""
