@@ -647,7 +647,7 @@ def main():
         import graphgen as gg
         cand = g.non_isolated() if sources is None else sources
         ps = gg.sample(cand, min(args.plain_sample, len(cand)), 7)
-        pst, pms = timed_compute(G, ps, stream, mode="plain", deg1=bool(prune))
+        pst, pms = timed_compute(G, ps, stream, mode="plain", deg1=bool(prune), alpha=args.alpha)
         pg = pst["te"] / (pms / 1e3) / 1e9
         pbytes = alg_bytes(n, tn, pst["launches"], pst)
         pk = pst["kernel_ms"]

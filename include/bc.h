@@ -149,7 +149,8 @@ typedef struct bc_compute_opts {
   uint32_t heuristics;  /* BC_H_* */
   int32_t sigma_mode;   /* BC_SIGMA_* */
   double alpha;         /* bottom-up when frontier edges * alpha > unvisited edges; 0 = default
-                           (tuned if available, else 1 batched / 4 plain), < 0 = never bottom-up */
+                           (tuned if available, else never: bottom-up levels were slower on every
+                           benchmarked graph), < 0 = never bottom-up */
   int32_t block;        /* threads per workgroup: 0, or the mode's fixed size (1024 batched, 256 plain) */
   int32_t grid_per_cu;  /* workgroups per CU for the persistent grid; 0 = the library's choice
                            (batched: one; plain: four when the traversed graph has at least 2^24

@@ -790,7 +790,7 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
   if (o->alpha > 0) r->alpha = o->alpha;
   else if (o->alpha < 0) r->alpha = 0.0;  // never bottom-up
   else if (g->tuned && !o->batch && r->mode == BC_MODE_BATCHED) r->alpha = g->tuned_alpha;
-  else r->alpha = r->mode == BC_MODE_PLAIN ? 4.0 : 1.0;
+  else r->alpha = 0.0;  // top-down only: bottom-up levels were slower on every graph measured
   if (o->beta < 0) return fail(BC_E_INVALID_ARG, "beta must be >= 0");
   r->beta = o->beta > 0 ? o->beta : (g->tuned && !o->batch && r->mode == BC_MODE_BATCHED ? g->tuned_beta : 0.0);
   return BC_OK;
@@ -1784,7 +1784,7 @@ bc_status bc_autotune(bc_graph* g, const int32_t* sample, int64_t k, bc_compute_
   if (s != BC_OK) return s;
   g->tuned = true;
   g->tuned_batch = best.batch;
-  g->tuned_alpha = best.alpha > 0 ? best.alpha : (best.alpha < 0 ? 0.0 : 1.0);
+  g->tuned_alpha = best.alpha > 0 ? best.alpha : 0.0;  // 0: never bottom-up
   g->tuned_grid = best.grid_per_cu;
   g->tuned_beta = best.beta;
   *opts = best;
