@@ -98,6 +98,8 @@ typedef struct bc_graph_stats {
   int64_t tree_vertices;   /* vertices removed by the iterated reduction (BC_LOAD_PRUNE_TREES) */
   int64_t bfs_depth;       /* levels of a breadth-first search from a highest-degree vertex (a lower
                               bound on the diameter; chooses the kernel under BC_MODE_AUTO) */
+  int64_t tuned_batch;     /* batch a call with batch = 0 uses: from bc_autotune on this graph or on
+                              a graph of the same shape in the context (0 = none tuned: 256) */
 } bc_graph_stats;
 
 /*
@@ -233,7 +235,11 @@ bc_status bc_compute_noalloc(bc_graph* g, const int32_t* sources, int64_t k, con
  * (mode, heuristics and sigma_mode are kept) and *gteps its throughput
  * (sample sources x m / time).  budget_ms bounds the tuning time (0 = no
  * bound beyond one pass).  The result is also remembered by the graph and
- * used by bc_compute calls whose opts->batch is 0.
+ * used by bc_compute calls whose opts->batch is 0, and kept in the context
+ * under the graph's shape (log2 of its non-isolated vertices, of its mean and
+ * largest degree; deep or not; with or without the 1-degree reduction), where
+ * graphs of the same shape that have no tuning of their own pick it up
+ * (bc_graph_stats.tuned_batch).
  */
 bc_status bc_autotune(bc_graph* g, const int32_t* sample, int64_t k, bc_compute_opts* opts, double budget_ms,
                       double* gteps);

@@ -37,7 +37,7 @@ EXPORTED = ["bc_context_create", "bc_context_destroy", "bc_graph_load", "bc_grap
 class GraphStats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in ("n", "m", "nnz", "isolated", "pendants", "k2_vertices",
                                                  "residual_nnz", "deg2_vertices", "max_degree", "resident_bytes",
-                                                 "tree_vertices", "bfs_depth")]
+                                                 "tree_vertices", "bfs_depth", "tuned_batch")]
 
 
 class ComputeOpts(ctypes.Structure):

@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <array>
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -299,11 +301,20 @@ size_t batch_layout(int64_t n, int64_t nnz, int B, int cap_factor, int max_slots
 
 // ------------------------------------------------------------------ objects
 
+// A batched-mode setting chosen by bc_autotune.
+struct TunedSet {
+  int32_t batch = 0, grid = 0;
+  double alpha = 0.0, beta = 0.0;
+};
+using ShapeKey = std::array<int64_t, 5>;
+
 struct bc_context {
   int device = 0;
   int cus = 0;
   std::string arch;
   uint64_t bar_ticks = 0;  // longest grid-barrier wait, in ticks of the device's wall clock
+  std::mutex tune_mu;
+  std::map<ShapeKey, TunedSet> tune_cache;  // bc_autotune results by graph shape
 };
 
 struct bc_graph {
@@ -504,6 +515,15 @@ void tree_scores_caller(const bc_graph* g, const int32_t* sources, int64_t k, st
   tree_scores(g->n, g->pr, isrc.data(), k, out->data());
   scores_to_caller(g, out->data());
 }
+
+// A graph's shape for the tuning cache: log2 of its non-isolated vertices,
+// of its mean and of its largest degree, whether it is deep (BC_MODE_AUTO's
+// test), and whether the call uses the 1-degree reduction.
+static ShapeKey shape_key(const bc_graph* g, bool deg1);
+
+// The tuned batched setting in effect for a graph: its own bc_autotune
+// result, else one tuned on a graph of the same shape in the context.
+static bool tuned_params(const bc_graph* g, bool deg1, TunedSet* t);
 
 }  // namespace bcx
 
@@ -733,6 +753,8 @@ bc_status bc_graph_stats_get(const bc_graph* g, bc_graph_stats* out) {
   out->max_degree = g->max_degree;
   out->tree_vertices = g->tree;
   out->bfs_depth = g->bfs_depth;
+  TunedSet tp;
+  out->tuned_batch = bcx::tuned_params(g, g->pruned, &tp) ? tp.batch : 0;
   out->resident_bytes = g->resident.load();
   return BC_OK;
 }
@@ -769,7 +791,9 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
   if (r->mode != BC_MODE_PLAIN && r->mode != BC_MODE_BATCHED && r->mode != BC_MODE_PLAIN_SCAN &&
       r->mode != BC_MODE_PER_WORKGROUP)
     return fail(BC_E_INVALID_ARG, "unknown mode");
-  r->B = o->batch ? o->batch : (g->tuned ? g->tuned_batch : 256);
+  TunedSet tp;
+  const bool tuned = tuned_params(g, (o->heuristics & BC_H_DEG1) != 0, &tp);
+  r->B = o->batch ? o->batch : (tuned ? tp.batch : 256);
   if (r->B % 64 != 0 || r->B < 64 || r->B > 64 * kMaxWords)
     return fail(BC_E_INVALID_ARG, "batch must be a multiple of 64 from 64 to 1024");
   r->K = r->B / 64;
@@ -777,7 +801,7 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
   r->block = o->block ? o->block : blk;
   if (r->block != blk)
     return fail(BC_E_INVALID_ARG, "block must be 1024 (batched, per_workgroup) or 256 (plain, plain_scan)");
-  r->grid_per_cu = o->grid_per_cu ? o->grid_per_cu : (g->tuned && !o->batch ? g->tuned_grid : 0);
+  r->grid_per_cu = o->grid_per_cu ? o->grid_per_cu : (tuned && !o->batch ? tp.grid : 0);
   r->sigma_mode = o->sigma_mode;
   if (r->sigma_mode < 0 || r->sigma_mode > 2) return fail(BC_E_INVALID_ARG, "unknown sigma mode");
   r->deg1 = (o->heuristics & BC_H_DEG1) != 0;
@@ -789,11 +813,35 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
     return fail(BC_E_INVALID_ARG, "BC_MODE_PLAIN_SCAN takes no heuristics and exact counts");
   if (o->alpha > 0) r->alpha = o->alpha;
   else if (o->alpha < 0) r->alpha = 0.0;  // never bottom-up
-  else if (g->tuned && !o->batch && r->mode == BC_MODE_BATCHED) r->alpha = g->tuned_alpha;
+  else if (tuned && !o->batch && r->mode == BC_MODE_BATCHED) r->alpha = tp.alpha;
   else r->alpha = 0.0;  // top-down only: bottom-up levels were slower on every graph measured
   if (o->beta < 0) return fail(BC_E_INVALID_ARG, "beta must be >= 0");
-  r->beta = o->beta > 0 ? o->beta : (g->tuned && !o->batch && r->mode == BC_MODE_BATCHED ? g->tuned_beta : 0.0);
+  r->beta = o->beta > 0 ? o->beta : (tuned && !o->batch && r->mode == BC_MODE_BATCHED ? tp.beta : 0.0);
   return BC_OK;
+}
+
+static ShapeKey shape_key(const bc_graph* g, bool deg1) {
+  auto lg = [](int64_t x) {
+    int64_t b = 0;
+    while (x > 1) { x >>= 1; ++b; }
+    return b;
+  };
+  const int64_t nv = std::max<int64_t>(1, g->n - g->isolated);
+  const int64_t nnz = deg1 ? g->rnnz : g->nnz;
+  return ShapeKey{lg(nv), lg(std::max<int64_t>(1, nnz / nv)), lg(g->max_degree + 1), g->bfs_depth > kLongDepth ? 1 : 0,
+                  deg1 ? 1 : 0};
+}
+
+static bool tuned_params(const bc_graph* g, bool deg1, TunedSet* t) {
+  if (g->tuned) {
+    *t = TunedSet{g->tuned_batch, g->tuned_grid, g->tuned_alpha, g->tuned_beta};
+    return true;
+  }
+  std::lock_guard<std::mutex> lk(g->ctx->tune_mu);
+  const auto it = g->ctx->tune_cache.find(shape_key(g, deg1));
+  if (it == g->ctx->tune_cache.end()) return false;
+  *t = it->second;
+  return true;
 }
 
 size_t ws_bytes_for(const bc_graph* g, const Resolved& r, int cap_factor) {
@@ -1787,6 +1835,11 @@ bc_status bc_autotune(bc_graph* g, const int32_t* sample, int64_t k, bc_compute_
   g->tuned_alpha = best.alpha > 0 ? best.alpha : 0.0;  // 0: never bottom-up
   g->tuned_grid = best.grid_per_cu;
   g->tuned_beta = best.beta;
+  {  // graphs of the same shape loaded later in this context start from it
+    std::lock_guard<std::mutex> tl(g->ctx->tune_mu);
+    g->ctx->tune_cache[shape_key(g, r0.deg1)] =
+        TunedSet{g->tuned_batch, g->tuned_grid, g->tuned_alpha, g->tuned_beta};
+  }
   *opts = best;
   if (gteps) *gteps = (double)credited * (double)(g->nnz / 2) / (best_ms * 1e-3) / 1e9;
   return BC_OK;

@@ -219,6 +219,26 @@ def test_tree_reduction_equals_unpruned(bcm, ctx, opts):
     G.close()
 
 
+def test_autotune_shared_by_graph_shape(bcm, ctx):
+    """A tuning is kept by graph shape in the context: a graph of the same
+    shape loaded afterwards starts from it (batch = 0 uses the tuned batch),
+    a graph of another shape does not; scores stay the oracle's."""
+    g = gg.rmat(11, 16, 12)
+    S = gg.sample(g.non_isolated(), 300, 5)
+    A = bcm.Graph(ctx, g)
+    tuned = A.autotune(S, budget_ms=20000)
+    B = bcm.Graph(ctx, g)  # the same shape, a new graph
+    C = bcm.Graph(ctx, gg.road_grid(40, 30, 0.05, 0.01, 3))
+    assert A.stats()["tuned_batch"] == tuned["batch"]
+    assert B.stats()["tuned_batch"] == tuned["batch"]
+    assert C.stats()["tuned_batch"] == 0
+    B.compute(S, batch=0)
+    ref, _ = oracle.bc(g, S)
+    assert_close(B.scores(), ref, what="tuned by shape")
+    for G in (A, B, C):
+        G.close()
+
+
 @pytest.mark.parametrize("batch", [64, 256])
 def test_degree2_derivation_equals_unpruned(bcm, ctx, batch):
     """2-degree vertices whose neighbours are sources of the same batch get
