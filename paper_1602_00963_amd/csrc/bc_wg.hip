@@ -15,14 +15,17 @@
 // mask of which of its neighbours are successors.  Exact counts are pushed by
 // atomic 64-bit adds whose returned value exposes a wrap; an extended count
 // (significand, exponent) is pulled by the thread that claimed the vertex,
-// from its neighbours on the current level, whose counts are final.
-// Backward (Alg. 4-5, successor checking): threads take the level's vertices
-// and sum psi = (1 + delta + omega) / sigma over the successors the mask
-// names; psi replaces the count in the record, which no later step reads.
-// Adjacency comes from a packed slot per vertex (degree and up to seven
-// neighbours in one 32-byte block), the CSR only for longer rows.  Scores are added with fp64
-// atomics (order-dependent rounding, within the 1e-9 tolerance).  The
-// touched records are cleared after each source.
+// from its neighbours on the current level, whose counts are final; the pull
+// also notes those predecessors in the new vertex's queue entry, so that its
+// own claim pass skips them.  Backward (Alg. 4-5, successor checking):
+// threads take the level's vertices and sum psi = (1 + delta + omega) /
+// sigma over the successors the mask names; psi replaces the count in the
+// record, which no later step reads.  Adjacency comes from a packed slot per
+// vertex (degree and up to seven neighbours in one 32-byte block), the CSR
+// only for longer rows.  Each source's contributions go to its own result
+// array with fp64 atomics (order-dependent rounding, within the 1e-9
+// tolerance).  Between sources the exact form clears the records it touched;
+// the extended form tags level words with a generation instead (below).
 #include "bc_common.h"
 #include "bc_kernels.h"
 #include "bc_wg.h"
