@@ -297,6 +297,20 @@ bc_status bc_prune_trees_host(int32_t n, const int32_t* row_ptr, const int32_t* 
                               int64_t k, int32_t* omega, int32_t* kind, double* scores, int64_t* res_nnz);
 
 /*
+ * The internal vertex order bc_graph_load would use, host only: perm[v] is
+ * the internal id of caller vertex v for these load_flags (by decreasing
+ * degree, ties by id; reverse Cuthill-McKee with BC_LOAD_ORDER_RCM; the
+ * identity with BC_LOAD_KEEP_ORDER), and *bfs_depth (if not NULL) the levels
+ * of a breadth-first search from the lowest-numbered vertex of highest
+ * degree, the figure BC_MODE_AUTO chooses the kernel by.  Only the CSR's
+ * bounds are checked
+ * (BC_E_INVALID_GRAPH if row_ptr[0] != 0, row_ptr decreases or a column
+ * index lies outside [0, n)); symmetry and sorted rows are assumed.
+ */
+bc_status bc_vertex_order_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t load_flags,
+                               int32_t* perm, int64_t* bfs_depth);
+
+/*
  * Heuristics coverage for all sources (the count the paper's heuristics
  * table reports), host only: with load_flags (BC_LOAD_PRUNE_DEG1 or
  * BC_LOAD_PRUNE_TREES) and heuristics (BC_H_DEG1, BC_H_DEG2) as bc_compute

@@ -31,7 +31,7 @@ EXPORTED = ["bc_context_create", "bc_context_destroy", "bc_graph_load", "bc_grap
             "bc_workspace_size", "bc_compute", "bc_scores", "bc_scores_reset", "bc_trace", "bc_validate_csr",
             "bc_prune_deg1_host", "bc_server_create", "bc_server_destroy", "bc_submit", "bc_wait",
             "bc_status_string", "bc_last_error", "bc_autotune", "bc_compute_noalloc",
-            "bc_server_stats_get", "bc_prune_trees_host", "bc_coverage_host"]
+            "bc_server_stats_get", "bc_prune_trees_host", "bc_coverage_host", "bc_vertex_order_host"]
 
 
 class GraphStats(ctypes.Structure):
@@ -121,6 +121,7 @@ def lib():
             "bc_server_stats_get": [vp, vp],
             "bc_prune_trees_host": [i32, vp, vp, vp, i64, vp, vp, vp, vp],
             "bc_coverage_host": [i32, vp, vp, u32, u32, vp],
+            "bc_vertex_order_host": [i32, vp, vp, u32, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -194,6 +195,18 @@ def coverage_host(n: int, row_ptr, col_idx, prune=False, deg1=False, deg2=False)
     _check(lib().bc_coverage_host(n, _p(rp), _p(ci), lf, (H_DEG1 if deg1 else 0) | (H_DEG2 if deg2 else 0),
                                   _p(out)), "bc_coverage_host")
     return dict(zip(["sources", "traversed", "one_degree", "two_degree", "deg2_candidates"], (int(x) for x in out)))
+
+
+def vertex_order_host(n: int, row_ptr, col_idx, order: str = "degree"):
+    """The internal vertex order the library would load the graph in (host
+    only): perm[v] = internal id of vertex v, for order "degree", "rcm" or
+    "keep"; and the BFS depth from a highest-degree vertex."""
+    rp, ci = _i32(row_ptr), _i32(col_idx)
+    lf = {"degree": 0, "rcm": LOAD_ORDER_RCM, "keep": LOAD_KEEP_ORDER}[order]
+    perm = np.zeros(n, np.int32)
+    depth = ctypes.c_int64(0)
+    _check(lib().bc_vertex_order_host(n, _p(rp), _p(ci), lf, _p(perm), ctypes.byref(depth)), "bc_vertex_order_host")
+    return perm, int(depth.value)
 
 
 class Context:

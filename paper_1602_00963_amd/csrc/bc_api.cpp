@@ -616,6 +616,32 @@ bc_status bc_prune_trees_host(int32_t n, const int32_t* row_ptr, const int32_t* 
   return BC_OK;
 }
 
+bc_status bc_vertex_order_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t load_flags,
+                               int32_t* perm, int64_t* bfs_depth) {
+  if (!row_ptr || !col_idx || n <= 0 || !perm) return fail(BC_E_INVALID_ARG, "bad arguments");
+  if (row_ptr[0] != 0) return fail(BC_E_INVALID_GRAPH, "row_ptr[0] must be 0");
+  for (int32_t v = 0; v < n; ++v)
+    if (row_ptr[v + 1] < row_ptr[v]) return fail(BC_E_INVALID_GRAPH, "row_ptr must be non-decreasing");
+  std::vector<int32_t> rp(row_ptr, row_ptr + n + 1), ci(col_idx, col_idx + row_ptr[n]);
+  for (int32_t u : ci)
+    if (u < 0 || u >= n) return fail(BC_E_INVALID_GRAPH, "column index out of range");
+  int32_t hub = 0;
+  int64_t maxd = -1;
+  for (int32_t v = 0; v < n; ++v)
+    if (rp[v + 1] - rp[v] > maxd) {
+      maxd = rp[v + 1] - rp[v];
+      hub = v;
+    }
+  if (bfs_depth) *bfs_depth = bfs_depth_from(n, rp.data(), ci.data(), hub);
+  if (load_flags & BC_LOAD_KEEP_ORDER) {
+    for (int32_t v = 0; v < n; ++v) perm[v] = v;
+    return BC_OK;
+  }
+  const std::vector<int32_t> order = (load_flags & BC_LOAD_ORDER_RCM) ? rcm_order(n, rp, ci) : degree_order(n, rp);
+  for (int32_t i = 0; i < n; ++i) perm[order[i]] = i;
+  return BC_OK;
+}
+
 bc_status bc_coverage_host(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, uint32_t load_flags,
                            uint32_t heuristics, int64_t* out) {
   if (!row_ptr || !col_idx || n < 0 || !out) return fail(BC_E_INVALID_ARG, "bad arguments");
