@@ -480,6 +480,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-graph", type=int, default=64,
+                    help="also time the plain leg with this many per-source launches per HIP graph (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, help="only run a copy of this many bytes")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving leg")
@@ -657,6 +659,15 @@ def main():
                         "achieved_GBs": round(pbytes / (pk / 1e3) / 1e9, 1)}
         out["batched_over_plain"] = round(gteps / pg, 2)
         log(f"plain: {pg:.2f} GTEPS on {len(ps)} sources")
+        if args.plain_graph > 0:
+            gst, gms = timed_compute(G, ps, stream, mode="plain", deg1=bool(prune), alpha=args.alpha,
+                                     graph_launches=args.plain_graph)
+            gg_te = gst["te"] / (gms / 1e3) / 1e9
+            out["plain"].update({"hip_graph_launches": args.plain_graph, "gteps_hip_graph": round(gg_te, 3),
+                                 "ms_hip_graph": round(gms, 1),
+                                 "per_launch_us_hip_graph": round(gms * 1e3 / max(gst["launches"], 1), 1),
+                                 "per_launch_us": round(pms * 1e3 / max(pst["launches"], 1), 1)})
+            log(f"plain from HIP graphs of {args.plain_graph} launches: {gg_te:.2f} GTEPS")
     if not args.no_serving:
         out["serving"] = serving_run(bcm, ctx, args.serving_graphs, args.serving_max_scale, args.serving_queries,
                                      args.serving_rho, args.serving_warmup, args.serving_inflight,

@@ -162,6 +162,11 @@ typedef struct bc_compute_opts {
   double beta;          /* switch back: a bottom-up sweep stays bottom-up until the frontier holds
                            fewer than n / beta vertices (batched: (vertex, word) entries against
                            n * words); 0 = no hysteresis (tuned if available), each level tests alpha */
+  int32_t graph_launches; /* BC_MODE_PLAIN: capture this many per-source launches in one HIP graph and
+                           replay it (every launch takes the next source of a device list, the rest
+                           of the list runs as single launches); 0 = one kernel launch per source.
+                           Only used when the call has at least that many sweeps; not allowed with
+                           other modes or bc_compute_noalloc, ignored by bc_trace */
 } bc_compute_opts;
 
 typedef struct bc_run_stats {

@@ -43,7 +43,7 @@ class GraphStats(ctypes.Structure):
 class ComputeOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("batch", ctypes.c_int32), ("heuristics", ctypes.c_uint32),
                 ("sigma_mode", ctypes.c_int32), ("alpha", ctypes.c_double), ("block", ctypes.c_int32),
-                ("grid_per_cu", ctypes.c_int32), ("beta", ctypes.c_double)]
+                ("grid_per_cu", ctypes.c_int32), ("beta", ctypes.c_double), ("graph_launches", ctypes.c_int32)]
 
 
 class RunStats(ctypes.Structure):
@@ -227,7 +227,8 @@ class Context:
             pass
 
 
-def make_opts(mode="batched", batch=256, deg1=False, deg2=False, sigma="auto", alpha=0.0, grid_per_cu=0, beta=0.0):
+def make_opts(mode="batched", batch=256, deg1=False, deg2=False, sigma="auto", alpha=0.0, grid_per_cu=0, beta=0.0,
+              graph_launches=0):
     o = ComputeOpts()
     o.mode = {v: k for k, v in MODE_NAMES.items()}[mode]
     o.batch = batch
@@ -237,6 +238,7 @@ def make_opts(mode="batched", batch=256, deg1=False, deg2=False, sigma="auto", a
     o.block = 0
     o.grid_per_cu = grid_per_cu
     o.beta = beta
+    o.graph_launches = graph_launches
     return o
 
 

@@ -18,6 +18,7 @@
 #include "bc_api_internal.h"
 #include "bc_host.h"
 #include "bc_kernels.h"
+#include "bc_plain.h"
 #include "bc_wg.h"
 
 using namespace bcx;
@@ -843,6 +844,9 @@ static bc_status resolve(const bc_graph* g, const bc_compute_opts* o, Resolved* 
   else r->alpha = 0.0;  // top-down only: bottom-up levels were slower on every graph measured
   if (o->beta < 0) return fail(BC_E_INVALID_ARG, "beta must be >= 0");
   r->beta = o->beta > 0 ? o->beta : (tuned && !o->batch && r->mode == BC_MODE_BATCHED ? tp.beta : 0.0);
+  if (o->graph_launches < 0 || (o->graph_launches > 0 && r->mode != BC_MODE_PLAIN))
+    return fail(BC_E_INVALID_ARG, "graph_launches must be >= 0 and is for BC_MODE_PLAIN only");
+  r->graph_launches = o->graph_launches;
   return BC_OK;
 }
 
@@ -1267,6 +1271,61 @@ bc_status run_batched(bc_graph* g, const Resolved& r, bool ext, const TravGraph&
   return BC_OK;
 }
 
+// The plain form's per-source launches from a HIP graph: k identical
+// launches captured once, replayed while k sources remain, each launch
+// taking the next source of a device list (the remainder runs as single
+// launches of the same form).  Returns after the stream has drained, since
+// the list is freed on the way out.
+static bc_status plain_replayed(const PlainArgs& a, bool ext, int grid, int block, const std::vector<Group>& groups,
+                                int k, hipStream_t st, Exec* ex, CallOut* out) {
+  const int64_t G = (int64_t)groups.size();
+  if (G > INT32_MAX) return fail(BC_E_INVALID_ARG, "too many sources for one device list");
+  std::vector<PlainSrc> h((size_t)G);
+  for (int64_t i = 0; i < G; ++i) h[i] = PlainSrc{groups[i].v, groups[i].own, groups[i].tsub, groups[i].w};
+  const size_t rec = (sizeof(PlainSrc) * (size_t)G + 255) / 256 * 256;
+  struct Held {
+    hipStream_t st;
+    hipStream_t cs = nullptr;
+    hipGraph_t gr = nullptr;
+    hipGraphExec_t ge = nullptr;
+    char* buf = nullptr;
+    ~Held() {
+      (void)hipStreamSynchronize(st);
+      if (ge) (void)hipGraphExecDestroy(ge);
+      if (gr) (void)hipGraphDestroy(gr);
+      if (cs) (void)hipStreamDestroy(cs);
+      if (buf) (void)hipFree(buf);
+    }
+  } held{st};
+  HIPCHK(hipMalloc(&held.buf, rec + 256));
+  const PlainFeed f{(const PlainSrc*)held.buf, (int32_t*)(held.buf + rec), (int32_t)G};
+  HIPCHK(hipMemcpyAsync(held.buf, h.data(), sizeof(PlainSrc) * (size_t)G, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(f.cursor, 0, sizeof(int32_t), st));
+  // captured on a stream of its own (the caller's may be the null stream)
+  HIPCHK(hipStreamCreateWithFlags(&held.cs, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(held.cs, hipStreamCaptureModeRelaxed));
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < k && e == hipSuccess; ++i) e = launch_plain_fed(a, f, ext, grid, block, held.cs);
+  const hipError_t e_end = hipStreamEndCapture(held.cs, &held.gr);
+  HIPCHK(e);
+  HIPCHK(e_end);
+  HIPCHK(hipGraphInstantiate(&held.ge, held.gr, nullptr, nullptr, 0));
+  const int64_t replays = G / k;
+  for (int64_t i = 0; i < replays + (G - replays * k); ++i) {
+    if (ex) HIPCHK(ex->mark(st));
+    if (i < replays) HIPCHK(hipGraphLaunch(held.ge, st));
+    else HIPCHK(launch_plain_fed(a, f, ext, grid, block, st));
+    if (!ex) continue;
+    HIPCHK(ex->mark(st));
+    if (ex->used >= 512) {
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(ex->collect(&out->kernel_ms));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return BC_OK;
+}
+
 bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& tg, const std::vector<Group>& groups,
                     char* wsbase, hipStream_t st, double* bc, double* delta_out, Exec* ex, CallOut* out) {
   if (ex) ex->used = 0;
@@ -1314,7 +1373,13 @@ bc_status run_plain(bc_graph* g, const Resolved& r, bool ext, const TravGraph& t
   a.cap_parts = (int32_t)plain_cap_parts(g->n, g->nnz);
   a.cap_multi = g->n;
   a.cap_levels = g->n + 3;
-  for (const auto& gr : groups) {
+  const bool replay = r.graph_launches > 0 && (int64_t)groups.size() >= r.graph_launches && !r.no_alloc;
+  if (replay) {
+    const bc_status s = plain_replayed(a, ext, grid, r.block, groups, r.graph_launches, st, ex, out);
+    if (s != BC_OK) return s;
+  }
+  for (size_t i = 0; !replay && i < groups.size(); ++i) {
+    const Group& gr = groups[i];
     a.src = gr.v;
     a.weight = gr.w;
     a.own = gr.own;
@@ -1684,6 +1749,7 @@ bc_status compute_noalloc(bc_graph* g, const int32_t* sources, int64_t k, const 
   bc_status s = resolve(g, opts, &r);
   if (s != BC_OK) return s;
   if (r.mode != BC_MODE_PLAIN) return fail(BC_E_INVALID_ARG, "bc_compute_noalloc runs the plain form only");
+  if (r.graph_launches) return fail(BC_E_INVALID_ARG, "bc_compute_noalloc takes no graph_launches (a graph allocates)");
   r.no_alloc = true;
   const size_t need = ws_bytes_for(g, r, r.cap_factor);
   if (need > scratch_bytes)
@@ -1903,6 +1969,7 @@ static bc_status trace_internal(bc_graph* g, const int32_t* sources, int64_t k, 
   if (r.mode == BC_MODE_PLAIN_SCAN || r.mode == BC_MODE_PER_WORKGROUP)
     return fail(BC_E_INVALID_ARG, "traces run in the plain or batched mode");
   r.trace = true;
+  r.graph_launches = 0;
   for (int64_t i = 0; i < k; ++i)
     if (sources[i] < 0 || sources[i] >= g->n) return fail(BC_E_INVALID_ARG, "source id out of range");
   HIPCHK(hipSetDevice(g->ctx->device));

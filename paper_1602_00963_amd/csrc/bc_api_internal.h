@@ -42,6 +42,7 @@ struct Resolved {
   int grid_total = 0;   // cap on the persistent grid's workgroups (the server's share of the device); 0 = none
   bool trace = false;   // parity traces: per-lane levels are kept (extra n * B int32)
   bool no_alloc = false;  // bc_compute_noalloc: no events, counters cleared by a fill kernel
+  int graph_launches = 0;  // plain form: per-source launches captured per HIP graph (0 = none)
 };
 bc_status resolve_opts(const bc_graph* g, const bc_compute_opts* o, Resolved* r);
 void graph_groups(const bc_graph* g, const Resolved& r, const int32_t* sources, int64_t k, std::vector<Group>* groups,

@@ -21,6 +21,7 @@
 //   depend on scheduling.
 #include "bc_common.h"
 #include "bc_kernels.h"
+#include "bc_plain.h"
 
 namespace bcx {
 
@@ -64,7 +65,16 @@ __device__ __forceinline__ void plain_finalize(const PlainArgs& a, int32_t w, do
 }
 
 template <bool EXT>
-__global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
+__global__ void __launch_bounds__(256) plain_kernel(PlainArgs a, PlainFeed f) {
+  if (f.srcs) {  // replayed launch: the next source of the device list
+    const int32_t k = *f.cursor;  // advanced by the previous launch on the stream
+    if (k >= f.nsrc) return;
+    const PlainSrc s = f.srcs[k];
+    a.src = s.v;
+    a.own = s.own;
+    a.tsub = s.tsub;
+    a.weight = s.weight;
+  }
   const int lane = lane_id();
   const int wpb = blockDim.x / kWave;
   const int gw = blockIdx.x * wpb + (int)(threadIdx.x / kWave);
@@ -338,13 +348,18 @@ __global__ void __launch_bounds__(256) plain_kernel(PlainArgs a) {
     *a.gmulti = 0;
     *a.ns = 0;
     *a.ovf_now = 0;
+    if (f.srcs) atomicAdd(f.cursor, 1);  // every wave read it before the first barrier
   }
 }
 
-hipError_t launch_plain(const PlainArgs& a, bool ext, int grid, int block, hipStream_t st) {
-  void* args[] = {(void*)&a};
+hipError_t launch_plain_fed(const PlainArgs& a, const PlainFeed& f, bool ext, int grid, int block, hipStream_t st) {
+  void* args[] = {(void*)&a, (void*)&f};
   const void* fn = ext ? (const void*)plain_kernel<true> : (const void*)plain_kernel<false>;
   return hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, st);
+}
+
+hipError_t launch_plain(const PlainArgs& a, bool ext, int grid, int block, hipStream_t st) {
+  return launch_plain_fed(a, PlainFeed{nullptr, nullptr, 0}, ext, grid, block, st);
 }
 
 hipError_t plain_max_grid(bool ext, int block, int* blocks_per_cu) {

@@ -181,6 +181,75 @@ def test_degree1_pruning_equals_unpruned(bcm, ctx, opts):
     assert_close(got_s, ref_s, what="pruned subset")
 
 
+@pytest.mark.parametrize("k", [64, 100], ids=["k64", "k100_ragged"])
+def test_plain_hip_graph_replay(bcm, ctx, k):
+    """Per-source launches replayed from a HIP graph (each launch takes the
+    next source of a device list) give the scores of single launches bit for
+    bit, over every source of an R-MAT graph (a ragged remainder with k =
+    100), twice in a row on the same graph, and the oracle's scores."""
+    g = gg.rmat(11, 8, 12)
+    say("case plain graph replay", k)
+    ref, _ = oracle.bc(g)
+    G = bcm.Graph(ctx, g)
+    st1 = G.compute(None, mode="plain")
+    direct = G.scores()
+    G.reset()
+    st2 = G.compute(None, mode="plain", graph_launches=k)
+    replayed = G.scores()
+    assert np.array_equal(replayed, direct)
+    assert st2["launches"] == st1["launches"] == st1["traversed"]
+    assert_close(replayed, ref, what="replayed scores")
+    # a second call on the same graph with fewer sources, then with fewer
+    # sources than one replay holds (single launches)
+    S = gg.sample(g.non_isolated(), 3 * k + 7, 5)
+    for src in (S, S[:k - 1]):
+        G.reset()
+        G.compute(src, mode="plain")
+        a = G.scores()
+        G.reset()
+        G.compute(src, mode="plain", graph_launches=k)
+        assert np.array_equal(G.scores(), a)
+        ref_s, _ = oracle.bc(g, src)
+        assert_close(G.scores(), ref_s, what=f"replayed subset of {len(src)}")
+    G.close()
+
+
+def test_plain_hip_graph_pruned_and_wrapping(bcm, ctx):
+    """Replayed launches carry the 1-degree reduction's folded sources and
+    subtree terms, and the extended rerun of wrapping sources."""
+    g = gg.disjoint_union(gg.rmat_with_pendants(10, 8, 3, 0.3, 33), gg.star(9), gg.path(2), gg.path(3))
+    say("case plain graph replay pruned")
+    ref, _ = oracle.bc(g)
+    a, _ = run_bc(bcm, ctx, g, prune=True, deg1=True, mode="plain")
+    b, st = run_bc(bcm, ctx, g, prune=True, deg1=True, mode="plain", graph_launches=32)
+    assert np.array_equal(a, b)
+    assert_close(b, ref, what="replayed pruned")
+    assert st["traversed"] < st["sources"]
+    # a 40 x 40 lattice: sources near the corners wrap uint64 and rerun
+    # extended, more of them than one replay holds
+    g = gg.full_grid(40, 40)
+    S = np.array([r * 40 + c for r in range(6) for c in range(6)] + [20 * 40 + 20, 19 * 40 + 21], np.int32)
+    say("case plain graph replay wrapping")
+    ref, ovf = oracle.bc(g, S)
+    assert ovf.sum() >= 16
+    a, _ = run_bc(bcm, ctx, g, S, mode="plain")
+    b, st = run_bc(bcm, ctx, g, S, mode="plain", graph_launches=8)
+    assert st["rerun_extended"] == int(ovf.sum())
+    assert np.array_equal(a, b)
+    assert_close(b, ref, what="replayed wrapping")
+
+
+def test_plain_hip_graph_option_checks(bcm, ctx):
+    g = gg.rmat(8, 8, 2)
+    G = bcm.Graph(ctx, g)
+    for opts in (dict(mode="plain", graph_launches=-1), dict(mode="batched", batch=64, graph_launches=8)):
+        with pytest.raises(bcm.BCError):
+            G.compute(None, **opts)
+    with pytest.raises(bcm.BCError):
+        G.compute_noalloc(None, mode="plain", graph_launches=8)
+    G.close()
+
+
 def tree_heavy_graph():
     return gg.disjoint_union(gg.attach_trees(gg.rmat(10, 4, 21), [1, 1, 2, 3, 5, 8, 13, 30, 60, 4, 4, 1, 1, 2], 7),
                              gg.random_tree(40, 3), gg.path(2), gg.star(6),
