@@ -333,9 +333,12 @@ bc_status bc_coverage_host(int32_t n, const int32_t* row_ptr, const int32_t* col
 typedef struct bc_server_config {
   int64_t hbm_budget_bytes;  /* device bytes the server may hold at once (workspaces and result
                                 arrays); 0 = 64 GiB */
-  int32_t max_inflight;      /* concurrent batches (streams); 0 = 4.  Each batch's grid is a
-                                1/max_inflight share of the device's resident workgroups, so the
-                                running batches co-run on the device.  Batches run in
+  int32_t max_inflight;      /* concurrent batches (streams); 0 = 4.  The device's resident
+                                workgroups are cut into max_inflight shares; a batch's grid takes
+                                one share, or, when no other query waits for a batch, every free
+                                share but one (one is kept for the next query to arrive); the
+                                running grids never hold more shares than there are, so they
+                                co-run on the device.  Batches run in
                                 BC_MODE_AUTO: graphs deeper than 64 levels one source per
                                 workgroup, the others batched */
   int32_t batch;             /* sources per batch, multiple of 64 up to 256; 0 = 256 */
@@ -355,6 +358,8 @@ typedef struct bc_server_stats {
   int64_t held_bytes;         /* device bytes held now (workspaces, result arrays, pool) */
   int64_t reclaims;           /* times pooled arrays / idle workspaces were given back */
   int64_t allocations;        /* device allocations made by the workers */
+  int64_t wide_batches;       /* batches whose grid took more than one share */
+  double mean_shares;         /* shares per batch, averaged over batches */
 } bc_server_stats;
 
 typedef struct bc_query_stats {

@@ -71,7 +71,7 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("workers", ctypes.c_int32), ("grid_workgroups", ctypes.c_int32),
                 ("max_inflight_seen", ctypes.c_int32), ("batches", ctypes.c_int64), ("mean_inflight", ctypes.c_double),
                 ("busy_ms", ctypes.c_double), ("held_bytes", ctypes.c_int64), ("reclaims", ctypes.c_int64),
-                ("allocations", ctypes.c_int64)]
+                ("allocations", ctypes.c_int64), ("wide_batches", ctypes.c_int64), ("mean_shares", ctypes.c_double)]
 
 
 class QueryStats(ctypes.Structure):

@@ -12,10 +12,14 @@
 // array has a single writer.
 //
 // Batches of different queries and graphs run at the same time on their
-// workers' streams: each worker's persistent grid is a 1/max_inflight share
-// of the workgroups the device keeps resident, so all running grids fit on
-// the device together (their grid barriers never wait for a workgroup that
-// another grid keeps out).
+// workers' streams.  The workgroups the device keeps resident are cut into
+// max_inflight shares and a batch's persistent grid holds whole shares, never
+// more than are free, so all running grids fit on the device together (their
+// grid barriers never wait for a workgroup that another grid keeps out).  A
+// batch takes one share while other queries wait for a batch; a query that
+// is alone takes every free share but one, the one left for the next query
+// to arrive, so a large query on an otherwise idle server is not held to a
+// quarter of the device.
 //
 // Device memory is never allocated or freed while the server lock is held:
 // admission and batch formation only do the accounting, the worker (or the
@@ -58,6 +62,8 @@ struct Query {
   double* out = nullptr;      // host result (caller-owned)
   size_t d_bytes = 0;         // result bytes (n doubles)
   int64_t ws_bytes = 0;       // workspace a batch of this query's graph needs
+  bool wide = false;          // its batches may take several shares (the batched form: a
+                              // workspace that does not grow with the grid)
   Buf res;                    // device result array (from the pool, or to be allocated)
   bool need_alloc = false;    // res is reserved in the budget but not allocated yet
   bool zeroed = false;
@@ -70,6 +76,7 @@ struct Query {
 
 struct Worker {
   std::thread th;
+  int shares = 0;  // shares of the device the current batch's grid holds
   hipStream_t st = nullptr;
   void* ws = nullptr;
   size_t ws_bytes = 0;
@@ -82,7 +89,8 @@ struct Worker {
 
 struct bc_server {
   int device = 0;
-  int grid_share = 0;  // workgroups of each worker's persistent grid
+  int grid_share = 0;  // workgroups of one share of the device
+  int free_shares = 0;
   bc_server_config cfg{};
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -98,7 +106,7 @@ struct bc_server {
   bool stop = false;
   // in-flight accounting
   int running = 0, max_running = 0;
-  int64_t batches = 0, reclaims = 0, allocations = 0;
+  int64_t batches = 0, reclaims = 0, allocations = 0, wide_batches = 0, share_sum = 0;
   double area_ms = 0.0, busy_ms = 0.0, last_change_ms = 0.0;
   Clock::time_point t0 = Clock::now();
   double now_ms() const { return std::chrono::duration<double, std::milli>(Clock::now() - t0).count(); }
@@ -126,12 +134,12 @@ bc_compute_opts serve_opts(const bc_server* s, const bc_graph* g) {
   return o;
 }
 
-bc_status serve_resolved(const bc_server* s, const bc_graph* g, Resolved* r) {
+bc_status serve_resolved(const bc_server* s, const bc_graph* g, int shares, Resolved* r) {
   bc_compute_opts o = serve_opts(s, g);
   bc_status st = resolve_opts(g, &o, r);
   r->cap_factor = r->B;  // worst-case level lists: a batch never runs out of them
   r->max_slots = 64;
-  r->grid_total = s->grid_share;
+  r->grid_total = s->grid_share * shares;
   return st;
 }
 
@@ -210,9 +218,13 @@ struct Job {
 // Forms the next batch; lock held.  Returns false if none can run now.
 bool take_job(bc_server* s, Worker* w, Job* job) {
   const int B = s->cfg.batch;
+  if (s->free_shares < 1) return false;
+  auto ready = [](const std::shared_ptr<Query>& q) {
+    return q->admitted && !q->running && !q->done && q->next < q->groups.size();
+  };
   std::shared_ptr<Query> lead;
   for (auto& q : s->queue)
-    if (q->admitted && !q->running && !q->done && q->next < q->groups.size()) { lead = q; break; }
+    if (ready(q)) { lead = q; break; }
   if (!lead) return false;
   const size_t need = (size_t)lead->ws_bytes;
   w->grow_to = 0;
@@ -229,7 +241,7 @@ bool take_job(bc_server* s, Worker* w, Job* job) {
   job->slots.clear();
   for (auto& q : s->queue) {
     if ((int)job->lanes.size() >= B || (int)job->slots.size() >= 64) break;
-    if (q->g != lead->g || !q->admitted || q->running || q->done || q->next >= q->groups.size()) continue;
+    if (q->g != lead->g || !ready(q)) continue;
     job->qs.push_back(q);
     q->running = true;
     if (q->start_ms < 0) q->start_ms = s->now_ms();
@@ -241,6 +253,14 @@ bool take_job(bc_server* s, Worker* w, Job* job) {
       job->lanes.push_back(gr);
     }
   }
+  // one share while another query waits for a batch, else all free but one
+  bool others = false;
+  for (auto& q : s->queue)
+    if (ready(q)) { others = true; break; }
+  w->shares = (others || !lead->wide) ? 1 : std::max(1, s->free_shares - 1);
+  s->free_shares -= w->shares;
+  s->share_sum += w->shares;
+  if (w->shares > 1) ++s->wide_batches;
   w->busy = true;
   s->note_running(+1);
   ++s->batches;
@@ -275,7 +295,7 @@ bc_status run_job(bc_server* s, Worker* w, Job& job, std::vector<std::shared_ptr
     job.slots[i] = (double*)q.res.p;
   }
   Resolved r;
-  bc_status st = serve_resolved(s, job.g, &r);
+  bc_status st = serve_resolved(s, job.g, w->shares, &r);
   const size_t cap = w->grow_to ? w->grow_to : w->ws_bytes;
   if (st == BC_OK)
     st = compute_groups(job.g, r, job.lanes, (int64_t)job.lanes.size(), w->ws, cap, w->st, job.slots.data(),
@@ -351,6 +371,8 @@ void worker_loop(bc_server* s, Worker* w) {
       if (st != BC_OK) q->status = st;
     }
     for (auto& q : complete) finish(s, q);
+    s->free_shares += w->shares;
+    w->shares = 0;
     w->busy = false;
     s->note_running(-1);
     admit(s);
@@ -383,6 +405,7 @@ bc_status bc_server_create(bc_context* ctx, const bc_server_config* cfg, bc_serv
   const int resident = context_cus(ctx) * occ;
   if (s->cfg.max_inflight > resident / 8) s->cfg.max_inflight = std::max(1, resident / 8);
   s->grid_share = resident / s->cfg.max_inflight;
+  s->free_shares = s->cfg.max_inflight;
   for (int i = 0; i < s->cfg.max_inflight; ++i) {
     auto w = std::make_unique<Worker>();
     if (hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking) != hipSuccess) {
@@ -430,9 +453,10 @@ bc_status bc_submit(bc_server* s, bc_graph* g, const int32_t* sources, int64_t k
   q->m = graph_nnz(g) / 2;
   q->d_bytes = sizeof(double) * (size_t)n;
   Resolved r;
-  bc_status st = serve_resolved(s, g, &r);
+  bc_status st = serve_resolved(s, g, 1, &r);
   if (st != BC_OK) return st;
   q->ws_bytes = (int64_t)graph_ws_bytes(g, r);
+  q->wide = r.mode == BC_MODE_BATCHED;
   graph_groups(g, r, sources, k, &q->groups, &q->credited);
   if (r.deg1) tree_scores_caller(g, sources, k, &q->tree);
   std::vector<Buf> frees;
@@ -496,6 +520,8 @@ bc_status bc_server_stats_get(bc_server* s, bc_server_stats* out) {
   out->held_bytes = s->held();
   out->reclaims = s->reclaims;
   out->allocations = s->allocations;
+  out->wide_batches = s->wide_batches;
+  out->mean_shares = s->batches ? (double)s->share_sum / (double)s->batches : 0.0;
   return BC_OK;
 }
 

@@ -234,6 +234,41 @@ def test_batches_run_concurrently(bcm, ctx):
         G.close()
 
 
+def test_lone_query_takes_free_shares(bcm, ctx):
+    """A query alone on the server runs its batches on every free share of
+    the device but one; queries arriving meanwhile start on the share left
+    free, and every result equals the query alone."""
+    big = gg.rmat(14, 16, 77)
+    small = gg.rmat(11, 8, 78)
+    Gb, Gs = bcm.Graph(ctx, big), bcm.Graph(ctx, small)
+    Sb = gg.sample(big.non_isolated(), 2048, 3)
+    srv = bcm.Server(ctx, max_inflight=4, batch=128)
+    say("case lone query: alone")
+    t = srv.submit(Gb, Sb)
+    srv.wait(t, timeout_us=300_000_000)
+    st = srv.stats()
+    say("server stats", st)
+    assert st["wide_batches"] == st["batches"] == 16
+    assert st["mean_shares"] == 3.0
+    assert oracle.close(t.out, alone(bcm, Gb, Sb), 1e-9).all()
+    say("case lone query: with arrivals")
+    t1 = srv.submit(Gb, Sb)
+    small_q = [(gg.sample(small.non_isolated(), 200, 10 + i)) for i in range(6)]
+    ts = [srv.submit(Gs, S) for S in small_q]
+    for x in [t1] + ts:
+        srv.wait(x, timeout_us=300_000_000)
+    st = srv.stats()
+    say("server stats", st)
+    srv.close()
+    assert 1.0 < st["mean_shares"] <= 3.0
+    assert oracle.close(t1.out, alone(bcm, Gb, Sb), 1e-9).all()
+    for S, x in zip(small_q, ts):
+        ref, _ = oracle.bc(small, S)
+        assert oracle.close(x.out, ref, 1e-9).all()
+    Gb.close()
+    Gs.close()
+
+
 @pytest.mark.parametrize("prune", [True, "trees"], ids=["one-round", "iterated"])
 def test_server_deg1_subsets(bcm, ctx, prune):
     """Queries on a pruned graph use the 1-degree reduction (one round, or
