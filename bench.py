@@ -358,17 +358,20 @@ def summarize_overlap(trace_dir: str, name: str, command: str) -> None:
         rows = [r for r in csv.DictReader(fh) if "batch_kernel" in r["Kernel_Name"]]
     ev = []
     for r in rows:
-        ev.append((int(r["Start_Timestamp"]), 1))
-        ev.append((int(r["End_Timestamp"]), -1))
-    ev.sort()
-    cur = best = 0
+        wg = int(r["Grid_Size_X"]) // max(int(r["Workgroup_Size_X"]), 1)
+        ev.append((int(r["Start_Timestamp"]), 1, wg))
+        ev.append((int(r["End_Timestamp"]), -1, wg))
+    ev.sort()  # at equal times, ends before starts
+    cur = best = cur_wg = best_wg = 0
     cover = {}
     last = ev[0][0] if ev else 0
-    for t, d in ev:
+    for t, d, wg in ev:
         if cur > 0:
             cover[cur] = cover.get(cur, 0) + (t - last)
         cur += d
+        cur_wg += d * wg
         best = max(best, cur)
+        best_wg = max(best_wg, cur_wg)
         last = t
     any_ns = sum(cover.values())
     multi_ns = sum(v for k, v in cover.items() if k >= 2)
@@ -380,7 +383,7 @@ def summarize_overlap(trace_dir: str, name: str, command: str) -> None:
         fo.write(f"- dispatches: {len(rows)} on {len(streams)} streams; workgroups per dispatch: {grids}\n")
         fo.write(f"- time with >= 1 dispatch running: {any_ns / 1e6:.1f} ms\n")
         fo.write(f"- time with >= 2 running: {multi_ns / 1e6:.1f} ms ({100.0 * multi_ns / max(any_ns, 1):.1f}%)\n")
-        fo.write(f"- most running at once: {best}\n")
+        fo.write(f"- most running at once: {best}; most workgroups running at once: {best_wg}\n")
         fo.write("- time by number running: " + ", ".join(f"{k}: {v / 1e6:.1f} ms" for k, v in sorted(cover.items()))
                  + "\n")
     print(open(out).read())
