@@ -398,8 +398,9 @@ bc_status bc_server_create(bc_context* ctx, const bc_server_config* cfg, bc_serv
   if (s->cfg.batch % 64 || s->cfg.batch > 256) { delete s; return fail(BC_E_INVALID_ARG, "batch must be 64..256, multiple of 64"); }
   if (s->cfg.heuristics & ~(uint32_t)BC_H_DEG1) { delete s; return fail(BC_E_INVALID_ARG, "the server takes BC_H_DEG1 only"); }
   // Persistent kernels wait at grid barriers for all their workgroups, so
-  // kernels running side by side must all fit on the device at once: each
-  // worker's grid is a 1/max_inflight share of the resident workgroups.
+  // kernels running side by side must all fit on the device at once: the
+  // resident workgroups are cut into max_inflight shares, and the grids
+  // running together never hold more shares than there are.
   const int occ = batch_occupancy(s->cfg.batch / 64);
   if (occ < 1) { delete s; return fail(BC_E_DEVICE, "occupancy query failed"); }
   const int resident = context_cus(ctx) * occ;

@@ -212,7 +212,8 @@ def test_idle_workspaces_do_not_block_admission(bcm, ctx):
 
 def test_batches_run_concurrently(bcm, ctx):
     """Queries on four graphs submitted together run as concurrent batches
-    (each on a quarter of the device); results equal each query alone."""
+    (each on one share of the device while others wait); results equal each
+    query alone."""
     graphs = [gg.rmat(12, 16, 300 + i) for i in range(4)]
     Gs = [bcm.Graph(ctx, g) for g in graphs]
     qs = [(i, gg.sample(graphs[i].non_isolated(), 768, 40 + i)) for i in range(4)] * 2
