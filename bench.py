@@ -345,17 +345,11 @@ def serving_run(bcm, ctx, n_graphs: int, max_scale: int, n_queries: int, rhos, w
     return out
 
 
-def summarize_overlap(trace_dir: str, name: str, command: str) -> None:
-    """Overlap of batch_kernel dispatches in a kernel trace: the time covered
-    by at least one dispatch, the time covered by two or more, and the most
-    running at once.  Writes profiles/<name>.md."""
-    import csv
-    import glob
-    f = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
-    if not f:
-        raise SystemExit(f"no kernel_trace.csv under {trace_dir}")
-    with open(f[0]) as fh:
-        rows = [r for r in csv.DictReader(fh) if "batch_kernel" in r["Kernel_Name"]]
+def overlap_stats(rows) -> dict:
+    """Concurrency of kernel dispatches (kernel-trace rows with start/end
+    timestamps and grid/workgroup sizes): time covered by k dispatches for
+    each k, and the most dispatches and workgroups running at once.  A
+    dispatch that starts when another ends does not overlap it."""
     ev = []
     for r in rows:
         wg = int(r["Grid_Size_X"]) // max(int(r["Workgroup_Size_X"]), 1)
@@ -373,19 +367,33 @@ def summarize_overlap(trace_dir: str, name: str, command: str) -> None:
         best = max(best, cur)
         best_wg = max(best_wg, cur_wg)
         last = t
-    any_ns = sum(cover.values())
-    multi_ns = sum(v for k, v in cover.items() if k >= 2)
-    streams = sorted({r["Stream_Id"] for r in rows})
-    grids = sorted({int(r["Grid_Size_X"]) // max(int(r["Workgroup_Size_X"]), 1) for r in rows})
+    return {"cover_ns": cover, "any_ns": sum(cover.values()),
+            "multi_ns": sum(v for k, v in cover.items() if k >= 2), "most": best, "most_workgroups": best_wg,
+            "streams": sorted({r["Stream_Id"] for r in rows}),
+            "grids": sorted({int(r["Grid_Size_X"]) // max(int(r["Workgroup_Size_X"]), 1) for r in rows})}
+
+
+def summarize_overlap(trace_dir: str, name: str, command: str) -> None:
+    """Overlap of batch_kernel dispatches in a kernel trace.  Writes
+    profiles/<name>.md."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no kernel_trace.csv under {trace_dir}")
+    with open(f[0]) as fh:
+        rows = [r for r in csv.DictReader(fh) if "batch_kernel" in r["Kernel_Name"]]
+    o = overlap_stats(rows)
+    any_ns, multi_ns = o["any_ns"], o["multi_ns"]
     out = os.path.join(ROOT, "profiles", f"{name}.md")
     with open(out, "w") as fo:
         fo.write(f"# Concurrent batch_kernel dispatches: {name}\n\n    {command}\n\n")
-        fo.write(f"- dispatches: {len(rows)} on {len(streams)} streams; workgroups per dispatch: {grids}\n")
+        fo.write(f"- dispatches: {len(rows)} on {len(o['streams'])} streams; workgroups per dispatch: {o['grids']}\n")
         fo.write(f"- time with >= 1 dispatch running: {any_ns / 1e6:.1f} ms\n")
         fo.write(f"- time with >= 2 running: {multi_ns / 1e6:.1f} ms ({100.0 * multi_ns / max(any_ns, 1):.1f}%)\n")
-        fo.write(f"- most running at once: {best}; most workgroups running at once: {best_wg}\n")
-        fo.write("- time by number running: " + ", ".join(f"{k}: {v / 1e6:.1f} ms" for k, v in sorted(cover.items()))
-                 + "\n")
+        fo.write(f"- most running at once: {o['most']}; most workgroups running at once: {o['most_workgroups']}\n")
+        fo.write("- time by number running: "
+                 + ", ".join(f"{k}: {v / 1e6:.1f} ms" for k, v in sorted(o["cover_ns"].items())) + "\n")
     print(open(out).read())
 
 
